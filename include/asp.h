@@ -1,0 +1,264 @@
+/*
+ * asp.h -- C ABI of libasp, a GPU (gfx950) implementation of the
+ * conflict-driven ASP solver of Dovier, Formisano and Vella,
+ * "GPU-based parallelism for ASP-solving".
+ *
+ * Problem (Sect. 2 and Alg. 1): given a ground normal program P, compute its
+ * completion nogoods Delta on the host, then search on the device for the
+ * first answer set (A^T restricted to atoms(P)) or report that none exists.
+ * The device search alternates PropagateAndCheck (Sect. 4.1, Alg. 2), the
+ * parallel Fwd-learning (Sect. 4.2, Alg. 4) with Backjump, and a Decision
+ * step that follows ASP computations (Sect. 2; Preliminaries), closing with
+ * CompleteAssignment.  A stability check of total assignments (M = least
+ * model of the Gelfond-Lifschitz reduct, the answer-set definition of the
+ * Preliminaries) turns unfounded models into conflicts.
+ *
+ * Conventions for every function below:
+ *  - all functions are extern "C", never throw, and return an int32 status;
+ *    negative values are errors, and asp_last_error() gives a message for the
+ *    calling thread;
+ *  - host arrays are owned by the caller and copied during the call;
+ *  - device memory is never allocated by the library: the caller passes a
+ *    device arena (e.g. a torch uint8 tensor) of the size the library asks
+ *    for, and must keep it alive while the handle uses it;
+ *  - "stream" is a hipStream_t passed as void* (NULL = default stream);
+ *  - one handle may be used by one thread at a time.
+ *
+ * Literals are signed int32: +v is "v true" (T v), -v is "v false" (F v).
+ * Variables 1..n_atoms are the program's atoms; headed rule j (0-based, in
+ * input order among headed rules) owns the auxiliary variables
+ * b_j = n_atoms+3j+1, t_j = n_atoms+3j+2, n_j = n_atoms+3j+3 of the
+ * completion (Sect. 2: b_r <-> t_r and n_r, t_r <-> body+, n_r <-> not body-).
+ */
+#ifndef ASP_H
+#define ASP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ statuses */
+#define ASP_OK           0
+#define ASP_SAT          1   /* an answer set was found */
+#define ASP_UNSAT        2   /* the program has no answer set */
+#define ASP_UNKNOWN      3   /* a budget or capacity limit stopped the search */
+#define ASP_FIXPOINT     4   /* propagation reached a fixpoint without conflict */
+#define ASP_CONFLICT     5   /* propagation found a conflict (pending analysis) */
+#define ASP_RUNNING      6   /* a step budget ended while the search is open */
+#define ASP_E_INVALID   -1   /* malformed input or argument */
+#define ASP_E_CAPACITY  -2   /* arena too small, or a size beyond the layout */
+#define ASP_E_DEVICE    -3   /* a HIP runtime call failed */
+#define ASP_E_STATE     -4   /* wrong call order for this handle */
+#define ASP_E_INTERNAL  -5   /* an internal consistency check failed */
+#define ASP_E_TIMEOUT   -6   /* the device-side wall-clock guard fired */
+
+/* Search step kinds, as reported by asp_run_steps. */
+#define ASP_STEP_NONE      0
+#define ASP_STEP_INIT      1  /* InitialPropagation (Alg. 1) */
+#define ASP_STEP_ROUND     2  /* one PropagateAndCheck round (Sect. 4.1) */
+#define ASP_STEP_LEARN     3  /* Fwd-learning + Backjump (Sect. 4.2, Alg. 1) */
+#define ASP_STEP_DECIDE    4  /* ASP-computation Decision (Sect. 2) */
+#define ASP_STEP_COMPLETE  5  /* CompleteAssignment (Sect. 2) */
+#define ASP_STEP_GATE      6  /* stability check of a total assignment */
+#define ASP_STEP_DONE      7
+
+#define ASP_GATE_UNFOUNDED 0  /* learn from the unfounded set's loop nogood */
+#define ASP_GATE_ALLDEC    1  /* learn the nogood of all current decisions */
+
+typedef struct asp_program asp_program;
+typedef struct asp_batch asp_batch;
+
+/* Structural options; they are part of the search semantics (the CPU
+ * reference must use the same values to reproduce a run). */
+typedef struct {
+    int32_t W;                 /* 64-bit words of the Deps bitmap per variable,
+                                  1..64; the decision at level l >= 2 sets bit
+                                  min(l-1, 64W-1) (Sect. 4.2) */
+    int32_t gate;              /* ASP_GATE_UNFOUNDED or ASP_GATE_ALLDEC */
+    int64_t learned_cap_ng;    /* learned nogoods kept per instance; exceeding
+                                  it ends the search with ASP_UNKNOWN */
+    int64_t learned_cap_lits;  /* learned literals kept per instance; idem */
+} asp_options;
+
+/* Run limits. */
+typedef struct {
+    int64_t max_conflicts;     /* <0 = unlimited; reaching it -> ASP_UNKNOWN */
+    int64_t max_ms;            /* device wall-clock guard per launch, <=0 none;
+                                  firing gives ASP_E_TIMEOUT for the instances
+                                  still open */
+} asp_limits;
+
+/* Launch schedule (no effect on results). */
+typedef struct {
+    int32_t threads;           /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    int32_t wg_per_cu;         /* persistent workgroups per compute unit, >= 1 */
+} asp_schedule;
+
+/* Search counters (the paper's Fig. 1/2 metrics plus literal checks).
+ * literal_checks = sum over every (propagated literal L, nogood containing L)
+ * visit of the nogood's length. */
+typedef struct {
+    int64_t rounds, visits, literal_checks, propagations, decisions, conflicts,
+            learned, learned_len, gate_failures, completes;
+    uint64_t trace_hash;       /* FNV-1a 64 over the decision/learning events */
+    int32_t status;            /* final status of the instance */
+    int32_t last_step;         /* ASP_STEP_* of the last step run */
+} asp_stats;
+
+typedef struct {
+    int32_t n_atoms;
+    int32_t n_rules_headed;
+    int32_t n_constraints;     /* constraints kept (tautologies dropped) */
+    int32_t n_vars;            /* n_atoms + 3 * n_rules_headed */
+    int64_t n_nogoods;         /* |Delta_0| */
+    int64_t n_lits;            /* literals over all nogoods of Delta_0 */
+    int64_t n_units;           /* nogoods of length 1 */
+    uint64_t device_bytes;     /* arena bytes asp_bind_device needs */
+} asp_sizes;
+
+/* Result of asp_propagate. */
+typedef struct {
+    int32_t status;            /* ASP_FIXPOINT or ASP_CONFLICT */
+    int32_t conflict_id;       /* selected conflict nogood (shortest, then
+                                  lowest id), -1 if none */
+    int64_t rounds;            /* rounds run by this call */
+    int64_t implied;           /* variables assigned by this call */
+    int64_t visits;            /* (literal, nogood) visits by this call */
+    int64_t literal_checks;    /* literal checks by this call */
+} asp_prop_result;
+
+/* Full solver state of a bound single program (test and checkpoint use). */
+typedef struct {
+    int32_t n_vars, W, cdl, frontier_len;
+    int32_t n_learned, pending;   /* pending: nogood id of a round conflict
+                                     awaiting asp_analyze_conflict, else -1 */
+    int64_t learned_lits;
+    int32_t initialised;          /* InitialPropagation has run */
+    int32_t status;               /* ASP_RUNNING while the search is open */
+    int8_t *val;                  /* [n_vars+1] -1 / 0 / +1 */
+    int32_t *lvl;                 /* [n_vars+1] decision level, 0 unassigned */
+    uint64_t *deps;               /* [(n_vars+1)*W] Deps bitmaps */
+    int32_t *dec;                 /* [cdl+1] decision literal of level l >= 2 */
+    int32_t *frontier;            /* [frontier_len] variables assigned by the
+                                     last step, ascending on export */
+    int32_t *learned_off;         /* [n_learned+1] */
+    int32_t *learned;             /* [learned_lits] */
+    asp_stats stats;
+} asp_state;
+
+/* --------------------------------------------------------- programs */
+
+/* Validate a ground program and compute its completion nogoods (Sect. 2).
+ *  head[r]    : head atom of rule r in 1..n_atoms, or 0 for a constraint
+ *  body_off   : n_rules+1 offsets, non-decreasing, body_off[0] = 0
+ *  body_lits  : +a (atom a) or -a (not a), 1 <= a <= n_atoms
+ *  opt        : NULL = {W=1, gate=UNFOUNDED, learned_cap_ng=1<<20,
+ *               learned_cap_lits=1<<22}
+ * Repeated body literals are removed (first kept); a constraint holding both
+ * a and not a is dropped.  Nogoods are generated per headed rule, then per
+ * atom, then per constraint, and stably sorted by length (Sect. 4); their
+ * position is their id.  On success *out owns a host-side handle (free it
+ * with asp_free_program) and *sizes (optional) is filled.
+ * Errors: ASP_E_INVALID before anything is allocated. */
+int32_t asp_load_program(int32_t n_atoms, int32_t n_rules, const int32_t *head,
+                         const int64_t *body_off, const int32_t *body_lits,
+                         const asp_options *opt, asp_program **out,
+                         asp_sizes *sizes);
+
+int32_t asp_free_program(asp_program *prog);
+
+/* Copy Delta_0 as CSR: off[n_nogoods+1], lits[n_lits] (host arrays). */
+int32_t asp_program_nogoods(const asp_program *prog, int32_t *off, int32_t *lits);
+
+/* Bind a device arena of at least sizes.device_bytes bytes (256-byte
+ * aligned) to the program, upload Delta_0, the literal-to-nogood map and the
+ * rule tables on `stream`, and reset the search state (nothing assigned).
+ * sched: NULL = 256 threads.  The arena must stay alive until the program is
+ * freed or bound again.  Errors: ASP_E_CAPACITY if bytes is too small,
+ * ASP_E_DEVICE on a HIP error. */
+int32_t asp_bind_device(asp_program *prog, void *dev_arena, uint64_t bytes,
+                        void *stream, const asp_schedule *sched);
+
+/* Run PropagateAndCheck rounds (Sect. 4.1) from the current state until a
+ * fixpoint, a conflict, or max_rounds rounds (max_rounds <= 0: no cap).
+ * Runs InitialPropagation first if it has not run.  Synchronous.
+ * Returns ASP_FIXPOINT, ASP_CONFLICT, ASP_RUNNING (round cap hit), ASP_UNSAT
+ * (clashing unit nogoods), or an error; *out (optional) gets the details. */
+int32_t asp_propagate(asp_program *prog, void *stream, int32_t max_rounds,
+                      asp_prop_result *out);
+
+/* Fwd-learning (Sect. 4.2) of the pending round conflict, then Backjump and
+ * assertion.  learned_lits (optional, cap entries) receives the learned
+ * nogood, *learned_len its length, *backjump_level the new level.
+ * Returns ASP_OK, ASP_UNSAT (the conflict depends on no decision),
+ * ASP_UNKNOWN (conflict budget or learned-store capacity), ASP_E_STATE (no
+ * pending conflict), ASP_E_CAPACITY (cap too small; the state is still
+ * updated).  Synchronous. */
+int32_t asp_analyze_conflict(asp_program *prog, void *stream,
+                             const asp_limits *lim, int32_t *learned_lits,
+                             int32_t cap, int32_t *learned_len,
+                             int32_t *backjump_level);
+
+/* Run the next n_steps search steps of any kind (n_steps < 0: to the end).
+ * Returns the search status (ASP_RUNNING if still open); *stats optional. */
+int32_t asp_run_steps(asp_program *prog, void *stream, const asp_limits *lim,
+                      int64_t n_steps, asp_stats *stats);
+
+/* Solve from scratch to the first answer set.  model (optional, n_atoms
+ * bytes, host) gets 1 for the true atoms when the result is ASP_SAT.
+ * Returns ASP_SAT, ASP_UNSAT, ASP_UNKNOWN or an error.  Synchronous. */
+int32_t asp_solve(asp_program *prog, void *stream, const asp_limits *lim,
+                  uint8_t *model, asp_stats *stats);
+
+/* State export: with st->val == NULL only the scalars are filled (to size
+ * the arrays); otherwise every non-NULL array is filled as well. */
+int32_t asp_state_export(asp_program *prog, void *stream, asp_state *st);
+
+/* State import (the frontier must hold variables of level cdl; the pending
+ * field may name a round conflict).  Errors: ASP_E_INVALID on inconsistent
+ * input, ASP_E_CAPACITY beyond the learned-store capacity. */
+int32_t asp_state_import(asp_program *prog, void *stream, const asp_state *st);
+
+/* ------------------------------------------------------------ batches */
+
+/* Plan one persistent launch over n programs (all loaded with the same W and
+ * gate option).  The programs must stay alive until asp_batch_bind returns.
+ * sched: NULL = {64 threads, 8 workgroups per CU}.  *device_bytes gets the
+ * arena size; *model_bytes (optional) the size of the model output, which
+ * holds instance i's n_atoms bytes after those of instances 0..i-1. */
+int32_t asp_batch_create(int32_t n, asp_program *const *progs,
+                         const asp_schedule *sched, asp_batch **out,
+                         uint64_t *device_bytes, uint64_t *model_bytes);
+
+/* Upload every program's static data into the arena (on stream). */
+int32_t asp_batch_bind(asp_batch *batch, void *dev_arena, uint64_t bytes,
+                       void *stream);
+
+/* Enqueue the batched solve on stream (asynchronous): one persistent launch
+ * in which each workgroup takes the largest open instance from a queue and
+ * solves it to a verdict.  Results stay in the arena. */
+int32_t asp_solve_batch(asp_batch *batch, void *stream, const asp_limits *lim);
+
+/* Copy verdicts[n] (ASP_SAT/UNSAT/UNKNOWN or a negative error),
+ * models[model_bytes] and stats[n] back (any may be NULL); synchronous. */
+int32_t asp_batch_results(asp_batch *batch, void *stream, int32_t *verdicts,
+                          uint8_t *models, asp_stats *stats);
+
+/* Kernel-only timing of the last asp_solve_batch launch, in milliseconds,
+ * measured with HIP events recorded on the launch stream. */
+int32_t asp_batch_last_ms(asp_batch *batch, double *ms);
+
+int32_t asp_batch_free(asp_batch *batch);
+
+/* ------------------------------------------------------------- misc */
+const char *asp_status_str(int32_t status);
+/* Copy the calling thread's last error message into buf (NUL-terminated). */
+int32_t asp_last_error(char *buf, uint64_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASP_H */

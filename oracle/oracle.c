@@ -1,0 +1,772 @@
+/*
+ * oracle.c -- plain sequential CPU oracle of the conflict-driven ASP solver
+ * (Dovier, Formisano, Vella: "GPU-based parallelism for ASP-solving").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may include, link
+ * or call this file; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark do.  It shares no code with the HIP library.
+ *
+ * It is written to be read against the paper, not to be fast: every step is
+ * the plain definition, with no blocking, fusion or reordering.  Where the
+ * paper leaves a choice open, the reading taken is stated at that step.
+ *
+ * Steps (one call of or_step runs exactly one):
+ *   INIT     -- InitialPropagation of the unit nogoods (Alg. 1, first kernel).
+ *   ROUND    -- one PropagateAndCheck round (Sect. 4.1, Alg. 2) in the
+ *               deterministic Jacobi reading: all nogoods reached from the
+ *               previous round's assignments are classified against one
+ *               snapshot, the lowest-id implier wins a variable, clashing
+ *               implications become conflicts.
+ *   LEARN    -- Fwd-learning (Sect. 4.2, Alg. 4) from the Deps bitmaps, then
+ *               Backjump (Alg. 1) and assertion of the complement of the most
+ *               recent decision in the learned nogood.
+ *   DECIDE   -- the ASP-computation Decision (Sect. 2): among rules r whose
+ *               head is unassigned with T t_r in A and F n_r not in A, pick the
+ *               highest occurrence count of the head (ties: lowest rule) and
+ *               assign T b_r at a new level.
+ *   COMPLETE -- CompleteAssignment (Sect. 2): no applicable rule is left, so
+ *               every unassigned original atom becomes false.
+ *   GATE     -- on a total assignment, check M = least model of the reduct
+ *               (the answer-set definition of the Preliminaries); a failure
+ *               becomes a conflict over the unfounded set's loop nogood.
+ *
+ * Readings of the paper taken here:
+ *   - levels start at 1 (root); the decision at level l >= 2 sets Deps bit
+ *     min(l-1, 64W-1), so bit 64W-1 stands for every level >= 64W;
+ *   - the learned nogood holds the decision literals of every level whose
+ *     bit is set in B = OR of the Deps of the conflict's variables; the
+ *     backjump level is the second-highest such level (1 if only one);
+ *   - T_Pi's second condition is read as body-(r) disjoint from I, the reduct
+ *     as Gelfond-Lifschitz, and the decided literal as T b_r (T n_r, not
+ *     F n_r, then follows by propagation);
+ *   - CompleteAssignment's falsifications take level cdl and the Deps of all
+ *     decisions.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OR_RUNNING = 0, OR_SAT = 1, OR_UNSAT = 2, OR_UNKNOWN = 3 };
+enum { OR_E_INVALID = -1, OR_E_INTERNAL = -5 };
+enum { ST_NONE = 0, ST_INIT = 1, ST_ROUND = 2, ST_LEARN = 3, ST_DECIDE = 4,
+       ST_COMPLETE = 5, ST_GATE = 6, ST_DONE = 7 };
+enum { GATE_UNFOUNDED = 0, GATE_ALLDEC = 1 };
+
+typedef struct {
+    int64_t rounds, visits, literal_checks, propagations, decisions, conflicts,
+            learned, learned_len, gate_failures, completes;
+    uint64_t trace_hash;
+} or_stats;
+
+typedef struct {
+    int64_t max_conflicts;     /* <0: unlimited */
+    int64_t learned_cap_ng;    /* <0: unlimited */
+    int64_t learned_cap_lits;  /* <0: unlimited */
+} or_limits;
+
+typedef struct { int32_t *a; int64_t n, cap; } ivec;
+
+static void iv_push(ivec *v, int32_t x) {
+    if (v->n == v->cap) {
+        v->cap = v->cap ? 2 * v->cap : 8;
+        v->a = (int32_t *)realloc(v->a, (size_t)v->cap * sizeof(int32_t));
+    }
+    v->a[v->n++] = x;
+}
+
+typedef struct {
+    /* program after normalisation */
+    int32_t A, Rh, Rc, V, W, gate_mode;
+    int32_t *rhead;            /* [Rh] head atom of headed rule j */
+    int32_t *pos_off, *pos;    /* body+ of headed rule j */
+    int32_t *neg_off, *neg;    /* body- of headed rule j */
+    int32_t has_empty_nogood;
+
+    /* nogoods: static ones first (ids 0..n0-1), learned ones appended */
+    int64_t n0, lits0;
+    ivec ng_off;               /* offsets, ng_off.a[i]..ng_off.a[i+1] */
+    ivec ng_lits;
+    ivec *map;                 /* [2(V+1)] literal -> nogood ids ascending */
+    int32_t *occ;              /* [A+1] static occurrence count */
+
+    /* assignment */
+    int8_t *val;
+    int32_t *lvl;
+    uint64_t *deps;            /* [(V+1)*W] */
+    int32_t cdl;
+    int32_t *dec;              /* [Rh+2] decision literal of each level */
+    ivec frontier;
+
+    /* pending conflict: kind 0 none, 1 round (id), 2 gate (bits) */
+    int32_t pend_kind;
+    int32_t pend_id;
+    uint64_t *pend_B;
+
+    int32_t status, last_step;
+    int64_t n_learned, learned_lits;
+    or_stats st;
+
+    /* scratch */
+    int32_t *win;              /* [V+1] min implier id, -1 none */
+    int8_t *winsign;           /* [V+1] value the winner implies */
+    int64_t nass;              /* number of assigned variables */
+    int32_t *touched;          /* [V+1] */
+    uint64_t *tmpdeps;         /* [(V+1)*W] */
+    int8_t *inM, *inLM;        /* [A+1] */
+} or_solver;
+
+/* ---------------------------------------------------------------- helpers */
+static inline int32_t var_of(int32_t lit) { return lit > 0 ? lit : -lit; }
+static inline int lit_index(int32_t lit) { return 2 * var_of(lit) + (lit < 0); }
+/* the value a literal asserts: +1 for T v, -1 for F v */
+static inline int8_t lit_sign(int32_t lit) { return lit > 0 ? 1 : -1; }
+
+static void fnv(or_solver *s, int32_t w) {
+    /* FNV-1a, 64 bit, over the 4 little-endian bytes of w */
+    uint32_t u = (uint32_t)w;
+    for (int k = 0; k < 4; ++k) {
+        s->st.trace_hash ^= (uint64_t)((u >> (8 * k)) & 0xffu);
+        s->st.trace_hash *= 1099511628211ull;
+    }
+}
+
+static int32_t ng_len(const or_solver *s, int64_t id) {
+    return s->ng_off.a[id + 1] - s->ng_off.a[id];
+}
+static const int32_t *ng_ptr(const or_solver *s, int64_t id) {
+    return s->ng_lits.a + s->ng_off.a[id];
+}
+
+static void add_nogood(or_solver *s, const int32_t *lits, int32_t n) {
+    int32_t id = (int32_t)(s->ng_off.n - 1);
+    for (int32_t k = 0; k < n; ++k) {
+        iv_push(&s->ng_lits, lits[k]);
+        iv_push(&s->map[lit_index(lits[k])], id);
+    }
+    iv_push(&s->ng_off, (int32_t)s->ng_lits.n);
+}
+
+/* bit of the decision at level l (l >= 2) */
+static inline int32_t level_bit(const or_solver *s, int32_t l) {
+    int32_t b = l - 1, top = 64 * s->W - 1;
+    return b < top ? b : top;
+}
+
+/* --------------------------------------------------------- S0/S1 encoding */
+/* Completion nogoods of the program (Sect. 2): for headed rule r with aux
+ * atoms b, t, n: {F b, T t, T n}, {T b, F t}, {T b, F n}, {T t, F p} per
+ * p in body+, {T n, T q} per q in body-, {F t} u {T p : body+},
+ * {F n} u {F q : body-}; per atom p: {F p, T b_r} per r in rules(p) and
+ * {T p} u {F b_r : r in rules(p)}; per constraint {T p : body+} u
+ * {F q : body-}.  Generated in that order, then stably sorted by length. */
+static int encode(or_solver *s, int32_t n_atoms, int32_t n_rules,
+                  const int32_t *head, const int64_t *body_off,
+                  const int32_t *body_lits) {
+    const int32_t A = n_atoms;
+    if (A < 0 || n_rules < 0) return OR_E_INVALID;
+    if (n_rules > 0 && body_off[0] != 0) return OR_E_INVALID;
+    for (int32_t r = 0; r < n_rules; ++r) {
+        if (body_off[r + 1] < body_off[r]) return OR_E_INVALID;
+        if (head[r] < 0 || head[r] > A) return OR_E_INVALID;
+        for (int64_t k = body_off[r]; k < body_off[r + 1]; ++k)
+            if (body_lits[k] == 0 || var_of(body_lits[k]) > A) return OR_E_INVALID;
+    }
+    int32_t Rh = 0;
+    for (int32_t r = 0; r < n_rules; ++r) Rh += head[r] != 0;
+    if ((int64_t)A + 3 * (int64_t)Rh > 0x3fffffff) return OR_E_INVALID;
+    s->A = A;
+    s->Rh = Rh;
+    s->V = A + 3 * Rh;
+
+    /* per headed rule: body+ and body- with repeated literals removed
+     * (first occurrence kept); constraints likewise, a constraint holding
+     * both p and not p is dropped (it can never be violated). */
+    int64_t tot = n_rules > 0 ? body_off[n_rules] : 0;
+    s->rhead = (int32_t *)calloc((size_t)Rh + 1, sizeof(int32_t));
+    s->pos_off = (int32_t *)calloc((size_t)Rh + 1, sizeof(int32_t));
+    s->neg_off = (int32_t *)calloc((size_t)Rh + 1, sizeof(int32_t));
+    s->pos = (int32_t *)calloc((size_t)tot + 1, sizeof(int32_t));
+    s->neg = (int32_t *)calloc((size_t)tot + 1, sizeof(int32_t));
+    int32_t *cpos_off = (int32_t *)calloc((size_t)n_rules + 1, sizeof(int32_t));
+    int32_t *cneg_off = (int32_t *)calloc((size_t)n_rules + 1, sizeof(int32_t));
+    int32_t *cpos = (int32_t *)calloc((size_t)tot + 1, sizeof(int32_t));
+    int32_t *cneg = (int32_t *)calloc((size_t)tot + 1, sizeof(int32_t));
+    int32_t np = 0, nn = 0, j = 0, ncp = 0, ncn = 0, c = 0;
+    for (int32_t r = 0; r < n_rules; ++r) {
+        int32_t p0 = head[r] ? np : ncp, n0 = head[r] ? nn : ncn;
+        int32_t *P = head[r] ? s->pos : cpos, *N = head[r] ? s->neg : cneg;
+        int32_t *pp = head[r] ? &np : &ncp, *pn = head[r] ? &nn : &ncn;
+        for (int64_t k = body_off[r]; k < body_off[r + 1]; ++k) {
+            int32_t l = body_lits[k], dup = 0;
+            for (int64_t k2 = body_off[r]; k2 < k; ++k2) dup |= body_lits[k2] == l;
+            if (dup) continue;
+            if (l > 0) P[(*pp)++] = l; else N[(*pn)++] = -l;
+        }
+        if (head[r]) {
+            s->rhead[j] = head[r];
+            s->pos_off[j + 1] = np;
+            s->neg_off[j + 1] = nn;
+            ++j;
+        } else {
+            int taut = 0;
+            for (int32_t a = p0; a < ncp; ++a)
+                for (int32_t b = n0; b < ncn; ++b) taut |= cpos[a] == cneg[b];
+            if (taut) { ncp = p0; ncn = n0; continue; }
+            cpos_off[c + 1] = ncp;
+            cneg_off[c + 1] = ncn;
+            ++c;
+        }
+    }
+    s->Rc = c;
+
+    /* generation order into a temporary CSR */
+    ivec goff = {0}, glits = {0}, tmp = {0};
+    iv_push(&goff, 0);
+#define FLUSH() do { for (int64_t q = 0; q < tmp.n; ++q) iv_push(&glits, tmp.a[q]); \
+                     iv_push(&goff, (int32_t)glits.n); tmp.n = 0; } while (0)
+    for (j = 0; j < Rh; ++j) {
+        int32_t b = A + 3 * j + 1, t = A + 3 * j + 2, n = A + 3 * j + 3;
+        iv_push(&tmp, -b); iv_push(&tmp, t); iv_push(&tmp, n); FLUSH();
+        iv_push(&tmp, b); iv_push(&tmp, -t); FLUSH();
+        iv_push(&tmp, b); iv_push(&tmp, -n); FLUSH();
+        for (int32_t k = s->pos_off[j]; k < s->pos_off[j + 1]; ++k) {
+            iv_push(&tmp, t); iv_push(&tmp, -s->pos[k]); FLUSH();
+        }
+        for (int32_t k = s->neg_off[j]; k < s->neg_off[j + 1]; ++k) {
+            iv_push(&tmp, n); iv_push(&tmp, s->neg[k]); FLUSH();
+        }
+        iv_push(&tmp, -t);
+        for (int32_t k = s->pos_off[j]; k < s->pos_off[j + 1]; ++k) iv_push(&tmp, s->pos[k]);
+        FLUSH();
+        iv_push(&tmp, -n);
+        for (int32_t k = s->neg_off[j]; k < s->neg_off[j + 1]; ++k) iv_push(&tmp, -s->neg[k]);
+        FLUSH();
+    }
+    /* rules(p) in input order, as a CSR over atoms */
+    int32_t *by_off = (int32_t *)calloc((size_t)A + 2, sizeof(int32_t));
+    int32_t *by = (int32_t *)calloc((size_t)Rh + 1, sizeof(int32_t));
+    for (j = 0; j < Rh; ++j) by_off[s->rhead[j] + 1] += 1;
+    for (int32_t p = 1; p <= A; ++p) by_off[p + 1] += by_off[p];
+    for (j = 0; j < Rh; ++j) by[by_off[s->rhead[j]]++] = j;
+    for (int32_t p = A; p >= 1; --p) by_off[p] = by_off[p - 1];
+    by_off[0] = 0;
+    for (int32_t p = 1; p <= A; ++p) {
+        for (int32_t k = by_off[p]; k < by_off[p + 1]; ++k) {
+            iv_push(&tmp, -p); iv_push(&tmp, A + 3 * by[k] + 1); FLUSH();
+        }
+        iv_push(&tmp, p);
+        for (int32_t k = by_off[p]; k < by_off[p + 1]; ++k) iv_push(&tmp, -(A + 3 * by[k] + 1));
+        FLUSH();
+    }
+    free(by_off);
+    free(by);
+    for (int32_t k = 0; k < c; ++k) {
+        for (int32_t q = cpos_off[k]; q < cpos_off[k + 1]; ++q) iv_push(&tmp, cpos[q]);
+        for (int32_t q = cneg_off[k]; q < cneg_off[k + 1]; ++q) iv_push(&tmp, -cneg[q]);
+        FLUSH();
+    }
+#undef FLUSH
+    int64_t G = goff.n - 1;
+
+    /* stable sort by length (Sect. 4: nogoods are stored by increasing
+     * length): a counting sort, which keeps generation order within a length */
+    int32_t maxlen = 0;
+    for (int64_t g = 0; g < G; ++g) {
+        int32_t L = goff.a[g + 1] - goff.a[g];
+        if (L > maxlen) maxlen = L;
+    }
+    int64_t *start = (int64_t *)calloc((size_t)maxlen + 2, sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(G > 0 ? G : 1));
+    for (int64_t g = 0; g < G; ++g) start[goff.a[g + 1] - goff.a[g] + 1] += 1;
+    for (int32_t L = 0; L <= maxlen; ++L) start[L + 1] += start[L];
+    for (int64_t g = 0; g < G; ++g) order[start[goff.a[g + 1] - goff.a[g]]++] = g;
+    s->map = (ivec *)calloc(2 * ((size_t)s->V + 1), sizeof(ivec));
+    iv_push(&s->ng_off, 0);
+    for (int64_t i = 0; i < G; ++i) {
+        int64_t g = order[i];
+        int32_t L = goff.a[g + 1] - goff.a[g];
+        if (L == 0) s->has_empty_nogood = 1;
+        add_nogood(s, glits.a + goff.a[g], L);
+    }
+    free(start);
+    free(order);
+    s->n0 = G;
+    s->lits0 = s->ng_lits.n;
+
+    s->occ = (int32_t *)calloc((size_t)A + 1, sizeof(int32_t));
+    for (int64_t g = 0; g < G; ++g) {
+        /* the atoms of a nogood are distinct, so each counts once per nogood */
+        for (int32_t k = s->ng_off.a[g]; k < s->ng_off.a[g + 1]; ++k) {
+            int32_t v = var_of(s->ng_lits.a[k]);
+            if (v <= A) s->occ[v] += 1;
+        }
+    }
+    free(goff.a); free(glits.a); free(tmp.a);
+    free(cpos_off); free(cneg_off); free(cpos); free(cneg);
+    return 0;
+}
+
+/* ------------------------------------------------------------- lifecycle */
+void or_free(void *h);
+
+void *or_create(int32_t n_atoms, int32_t n_rules, const int32_t *head,
+                const int64_t *body_off, const int32_t *body_lits,
+                int32_t W, int32_t gate_mode, int32_t *err) {
+    if (W < 1 || W > 1024 || (gate_mode != GATE_UNFOUNDED && gate_mode != GATE_ALLDEC)) {
+        if (err) *err = OR_E_INVALID;
+        return NULL;
+    }
+    or_solver *s = (or_solver *)calloc(1, sizeof(or_solver));
+    s->W = W;
+    s->gate_mode = gate_mode;
+    int rc = encode(s, n_atoms, n_rules, head, body_off, body_lits);
+    if (rc) {
+        or_free(s);
+        if (err) *err = rc;
+        return NULL;
+    }
+    size_t V1 = (size_t)s->V + 1;
+    s->val = (int8_t *)calloc(V1, 1);
+    s->lvl = (int32_t *)calloc(V1, sizeof(int32_t));
+    s->deps = (uint64_t *)calloc(V1 * W, sizeof(uint64_t));
+    s->tmpdeps = (uint64_t *)calloc(V1 * W, sizeof(uint64_t));
+    s->pend_B = (uint64_t *)calloc((size_t)W, sizeof(uint64_t));
+    s->dec = (int32_t *)calloc((size_t)s->Rh + 2, sizeof(int32_t));
+    s->win = (int32_t *)malloc(V1 * sizeof(int32_t));
+    for (size_t v = 0; v < V1; ++v) s->win[v] = -1;
+    s->touched = (int32_t *)calloc(V1, sizeof(int32_t));
+    s->winsign = (int8_t *)calloc(V1, 1);
+    s->inM = (int8_t *)calloc((size_t)s->A + 1, 1);
+    s->inLM = (int8_t *)calloc((size_t)s->A + 1, 1);
+    s->cdl = 1;
+    s->st.trace_hash = 1469598103934665603ull;
+    s->status = OR_RUNNING;
+    s->last_step = ST_NONE;
+    if (err) *err = 0;
+    return s;
+}
+
+void or_free(void *h) {
+    or_solver *s = (or_solver *)h;
+    if (!s) return;
+    free(s->rhead); free(s->pos_off); free(s->pos); free(s->neg_off); free(s->neg);
+    free(s->ng_off.a); free(s->ng_lits.a);
+    if (s->map)
+        for (size_t i = 0; i < 2 * ((size_t)s->V + 1); ++i) free(s->map[i].a);
+    free(s->map); free(s->occ);
+    free(s->val); free(s->lvl); free(s->deps); free(s->tmpdeps); free(s->pend_B);
+    free(s->dec); free(s->frontier.a); free(s->win); free(s->winsign); free(s->touched);
+    free(s->inM); free(s->inLM);
+    free(s);
+}
+
+/* ------------------------------------------------------------------ steps */
+static int cmp_i32(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* S3: every unit nogood {l}, in id order, assigns the complement of l at
+ * level 1 with empty Deps; two opposite units mean no answer set. */
+static void step_init(or_solver *s) {
+    if (s->has_empty_nogood) { s->status = OR_UNSAT; return; }
+    s->frontier.n = 0;
+    for (int64_t id = 0; id < s->n0 && ng_len(s, id) <= 1; ++id) {
+        if (ng_len(s, id) != 1) continue;
+        int32_t l = ng_ptr(s, id)[0], x = var_of(l);
+        int8_t want = (int8_t)-lit_sign(l);
+        if (s->val[x] == 0) {
+            s->val[x] = want;
+            s->lvl[x] = 1;
+            s->nass += 1;
+            iv_push(&s->frontier, x);
+        } else if (s->val[x] != want) {
+            s->status = OR_UNSAT;
+            return;
+        }
+    }
+    qsort(s->frontier.a, (size_t)s->frontier.n, sizeof(int32_t), cmp_i32);
+}
+
+/* Classification of nogood id against the current assignment:
+ * 0 = other (satisfied or more than one open literal), 1 = violated,
+ * 2 = unit; for unit, *u is the open literal. */
+static int classify(const or_solver *s, int64_t id, int32_t *u) {
+    const int32_t *L = ng_ptr(s, id);
+    int32_t n = ng_len(s, id), open = 0, in = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        int8_t v = s->val[var_of(L[k])];
+        if (v == 0) { ++open; *u = L[k]; }
+        else if (v == lit_sign(L[k])) ++in;
+    }
+    if (in == n) return 1;
+    if (open == 1 && in == n - 1) return 2;
+    return 0;
+}
+
+/* S4: one PropagateAndCheck round (Sect. 4.1) in Jacobi form.
+ * S5: among the round's conflicts, keep the shortest, ties by lowest id. */
+static void step_round(or_solver *s) {
+    const int32_t W = s->W;
+    int64_t best_len = -1, best_id = -1;
+    int32_t nt = 0;
+    /* phase 1: classify every visit against the snapshot, find winners */
+    for (int64_t f = 0; f < s->frontier.n; ++f) {
+        int32_t v = s->frontier.a[f];
+        int32_t L = s->val[v] > 0 ? v : -v;
+        const ivec *m = &s->map[lit_index(L)];
+        for (int64_t q = 0; q < m->n; ++q) {
+            int32_t id = m->a[q], u = 0;
+            s->st.visits += 1;
+            s->st.literal_checks += ng_len(s, id);
+            int c = classify(s, id, &u);
+            if (c == 1) {
+                if (best_id < 0 || ng_len(s, id) < best_len ||
+                    (ng_len(s, id) == best_len && id < best_id)) {
+                    best_len = ng_len(s, id);
+                    best_id = id;
+                }
+            } else if (c == 2) {
+                int32_t x = var_of(u);
+                if (s->win[x] < 0) s->touched[nt++] = x;
+                if (s->win[x] < 0 || id < s->win[x]) {
+                    s->win[x] = id;
+                    s->winsign[x] = (int8_t)-lit_sign(u);
+                }
+            }
+        }
+    }
+    /* phase 2: a unit nogood implying the other value than its variable's
+     * winner is a conflict (the clash of Alg. 2, made deterministic) */
+    for (int64_t f = 0; f < s->frontier.n; ++f) {
+        int32_t v = s->frontier.a[f];
+        int32_t L = s->val[v] > 0 ? v : -v;
+        const ivec *m = &s->map[lit_index(L)];
+        for (int64_t q = 0; q < m->n; ++q) {
+            int32_t id = m->a[q], u = 0;
+            if (classify(s, id, &u) != 2) continue;
+            int32_t x = var_of(u);
+            if (s->winsign[x] != -lit_sign(u)) {
+                if (best_id < 0 || ng_len(s, id) < best_len ||
+                    (ng_len(s, id) == best_len && id < best_id)) {
+                    best_len = ng_len(s, id);
+                    best_id = id;
+                }
+            }
+        }
+    }
+    /* phase 3: Deps of each implied variable = OR of the Deps of the other
+     * variables of its winning nogood (mk_dl_bitmap), all read before any
+     * write so that they come from the snapshot */
+    qsort(s->touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+    for (int32_t i = 0; i < nt; ++i) {
+        int32_t x = s->touched[i], w = s->win[x];
+        uint64_t *d = s->tmpdeps + (size_t)i * W;
+        memset(d, 0, sizeof(uint64_t) * W);
+        const int32_t *L = ng_ptr(s, w);
+        for (int32_t k = 0; k < ng_len(s, w); ++k) {
+            int32_t y = var_of(L[k]);
+            if (y == x) continue;
+            for (int32_t q = 0; q < W; ++q) d[q] |= s->deps[(size_t)y * W + q];
+        }
+    }
+    /* phase 4: apply every implication, even when a conflict was found */
+    for (int32_t i = 0; i < nt; ++i) {
+        int32_t x = s->touched[i];
+        s->val[x] = s->winsign[x];
+        s->lvl[x] = s->cdl;
+        memcpy(s->deps + (size_t)x * W, s->tmpdeps + (size_t)i * W, sizeof(uint64_t) * W);
+    }
+    for (int32_t i = 0; i < nt; ++i) s->win[s->touched[i]] = -1;
+    s->frontier.n = 0;
+    for (int32_t i = 0; i < nt; ++i) iv_push(&s->frontier, s->touched[i]);
+    s->nass += nt;
+    s->st.rounds += 1;
+    s->st.propagations += nt;
+    if (best_id >= 0) {
+        s->pend_kind = 1;
+        s->pend_id = (int32_t)best_id;
+    }
+}
+
+/* S6 + S7: Fwd-learning (Alg. 4) followed by Backjump and assertion. */
+static void step_learn(or_solver *s, const or_limits *lim) {
+    const int32_t W = s->W;
+    uint64_t *B = s->pend_B;
+    if (s->pend_kind == 1) {
+        memset(B, 0, sizeof(uint64_t) * W);
+        const int32_t *L = ng_ptr(s, s->pend_id);
+        for (int32_t k = 0; k < ng_len(s, s->pend_id); ++k) {
+            int32_t y = var_of(L[k]);
+            for (int32_t q = 0; q < W; ++q) B[q] |= s->deps[(size_t)y * W + q];
+        }
+    }
+    int zero = 1;
+    for (int32_t q = 0; q < W; ++q) zero &= B[q] == 0;
+    if (zero) {
+        /* the conflict follows from level-1 facts alone */
+        s->st.conflicts += 1;
+        s->status = OR_UNSAT;
+        return;
+    }
+    if (lim && lim->max_conflicts >= 0 && s->st.conflicts >= lim->max_conflicts) {
+        s->status = OR_UNKNOWN;
+        return;
+    }
+    s->st.conflicts += 1;
+    /* levels(B), ascending: level l in 2..64W-1 for bit l-1, plus every
+     * level 64W..cdl when the saturated bit 64W-1 is set */
+    ivec lev = {0};
+    for (int32_t l = 2; l <= s->cdl; ++l) {
+        int32_t b = level_bit(s, l);
+        if ((B[b / 64] >> (b % 64)) & 1u) iv_push(&lev, l);
+    }
+    int64_t nN = lev.n;
+    if ((lim && lim->learned_cap_ng >= 0 && s->n_learned + 1 > lim->learned_cap_ng) ||
+        (lim && lim->learned_cap_lits >= 0 && s->learned_lits + nN > lim->learned_cap_lits)) {
+        free(lev.a);
+        s->status = OR_UNKNOWN;
+        return;
+    }
+    int32_t *N = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nN > 0 ? nN : 1));
+    for (int64_t i = 0; i < nN; ++i) N[i] = s->dec[lev.a[i]];
+    int32_t topl = lev.a[nN - 1];
+    int32_t bj = nN >= 2 ? lev.a[nN - 2] : 1;
+    int32_t toplit = s->dec[topl];
+    add_nogood(s, N, (int32_t)nN);
+    s->n_learned += 1;
+    s->learned_lits += nN;
+    s->st.learned += 1;
+    s->st.learned_len += nN;
+    fnv(s, 2); fnv(s, s->pend_kind == 1 ? s->pend_id : -1); fnv(s, (int32_t)nN); fnv(s, bj);
+    /* Backjump: unassign everything above bj */
+    for (int32_t v = 1; v <= s->V; ++v)
+        if (s->lvl[v] > bj) {
+            s->nass -= s->val[v] != 0;
+            s->val[v] = 0;
+            s->lvl[v] = 0;
+            memset(s->deps + (size_t)v * W, 0, sizeof(uint64_t) * W);
+        }
+    s->cdl = bj;
+    /* assert the complement of the latest decision at level bj */
+    int32_t x = var_of(toplit);
+    s->nass += 1;
+    s->val[x] = (int8_t)-lit_sign(toplit);
+    s->lvl[x] = bj;
+    uint64_t *d = s->deps + (size_t)x * W;
+    memset(d, 0, sizeof(uint64_t) * W);
+    for (int64_t i = 0; i + 1 < nN; ++i) {
+        int32_t y = var_of(N[i]);
+        for (int32_t q = 0; q < W; ++q) d[q] |= s->deps[(size_t)y * W + q];
+    }
+    s->frontier.n = 0;
+    iv_push(&s->frontier, x);
+    s->pend_kind = 0;
+    s->pend_id = -1;
+    free(N);
+    free(lev.a);
+}
+
+/* S8: pick an applicable rule (T t_r in A, F n_r not in A, head unassigned)
+ * by the highest occurrence count of its head, ties to the lowest rule. */
+static int32_t find_decision(const or_solver *s) {
+    int32_t best = -1, bestocc = -1;
+    for (int32_t j = 0; j < s->Rh; ++j) {
+        int32_t p = s->rhead[j], t = s->A + 3 * j + 2, n = s->A + 3 * j + 3;
+        if (s->val[p] != 0 || s->val[t] != 1 || s->val[n] == -1) continue;
+        if (s->occ[p] > bestocc) { bestocc = s->occ[p]; best = j; }
+    }
+    return best;
+}
+
+static void step_decide(or_solver *s, int32_t j) {
+    const int32_t W = s->W;
+    int32_t b = s->A + 3 * j + 1;
+    s->cdl += 1;
+    s->dec[s->cdl] = b;
+    s->nass += 1;
+    s->val[b] = 1;
+    s->lvl[b] = s->cdl;
+    uint64_t *d = s->deps + (size_t)b * W;
+    memset(d, 0, sizeof(uint64_t) * W);
+    int32_t bit = level_bit(s, s->cdl);
+    d[bit / 64] |= 1ull << (bit % 64);
+    s->frontier.n = 0;
+    iv_push(&s->frontier, b);
+    s->st.decisions += 1;
+    fnv(s, 1); fnv(s, j);
+}
+
+/* S9: CompleteAssignment -- every unassigned original atom becomes false at
+ * level cdl, depending on every decision made so far. */
+static void step_complete(or_solver *s) {
+    const int32_t W = s->W;
+    s->frontier.n = 0;
+    for (int32_t p = 1; p <= s->A; ++p) {
+        if (s->val[p] != 0) continue;
+        s->val[p] = -1;
+        s->nass += 1;
+        s->lvl[p] = s->cdl;
+        uint64_t *d = s->deps + (size_t)p * W;
+        memset(d, 0, sizeof(uint64_t) * W);
+        for (int32_t l = 2; l <= s->cdl; ++l) {
+            int32_t bit = level_bit(s, l);
+            d[bit / 64] |= 1ull << (bit % 64);
+        }
+        iv_push(&s->frontier, p);
+    }
+    s->st.completes += 1;
+    fnv(s, 3); fnv(s, (int32_t)s->frontier.n);
+    if (s->frontier.n == 0) s->status = OR_E_INTERNAL;
+}
+
+/* S10: M = true original atoms; M is an answer set iff M equals the least
+ * model of the reduct (rules whose body- misses M, with body- deleted). */
+static void step_gate(or_solver *s) {
+    const int32_t A = s->A, W = s->W;
+    for (int32_t p = 1; p <= A; ++p) { s->inM[p] = s->val[p] == 1; s->inLM[p] = 0; }
+    for (int changed = 1; changed;) {
+        changed = 0;
+        for (int32_t j = 0; j < s->Rh; ++j) {
+            int32_t h = s->rhead[j], ok = !s->inLM[h];
+            for (int32_t k = s->neg_off[j]; ok && k < s->neg_off[j + 1]; ++k) ok = !s->inM[s->neg[k]];
+            for (int32_t k = s->pos_off[j]; ok && k < s->pos_off[j + 1]; ++k) ok = s->inLM[s->pos[k]];
+            if (ok) { s->inLM[h] = 1; changed = 1; }
+        }
+    }
+    int32_t u = 0;
+    for (int32_t p = 1; p <= A && !u; ++p)
+        if (s->inM[p] && !s->inLM[p]) u = p;
+    if (!u) { s->status = OR_SAT; return; }
+    s->st.gate_failures += 1;
+    uint64_t *B = s->pend_B;
+    memset(B, 0, sizeof(uint64_t) * W);
+    if (s->gate_mode == GATE_ALLDEC) {
+        for (int32_t l = 2; l <= s->cdl; ++l) {
+            int32_t bit = level_bit(s, l);
+            B[bit / 64] |= 1ull << (bit % 64);
+        }
+    } else {
+        /* loop nogood of U = M \ LM: T u together with F b_r for every
+         * external support r (head in U, body+ disjoint from U) */
+        for (int32_t q = 0; q < W; ++q) B[q] |= s->deps[(size_t)u * W + q];
+        for (int32_t j = 0; j < s->Rh; ++j) {
+            int32_t h = s->rhead[j];
+            if (!(s->inM[h] && !s->inLM[h])) continue;
+            int ext = 1;
+            for (int32_t k = s->pos_off[j]; ext && k < s->pos_off[j + 1]; ++k) {
+                int32_t p = s->pos[k];
+                ext = !(s->inM[p] && !s->inLM[p]);
+            }
+            if (!ext) continue;
+            int32_t b = A + 3 * j + 1;
+            for (int32_t q = 0; q < W; ++q) B[q] |= s->deps[(size_t)b * W + q];
+        }
+    }
+    s->pend_kind = 2;
+    s->pend_id = -1;
+}
+
+/* ----------------------------------------------------------- public API */
+/* which step comes next; *j gets the chosen rule for a decision */
+static int32_t next_step(or_solver *s, int32_t *j) {
+    *j = -1;
+    if (s->status != OR_RUNNING) return ST_DONE;
+    if (s->last_step == ST_NONE) return ST_INIT;
+    if (s->pend_kind) return ST_LEARN;
+    if (s->frontier.n > 0) return ST_ROUND;
+    if (s->nass == s->V) return ST_GATE;
+    *j = find_decision(s);
+    return *j >= 0 ? ST_DECIDE : ST_COMPLETE;
+}
+
+int32_t or_next_step(void *h) {
+    int32_t j;
+    return next_step((or_solver *)h, &j);
+}
+
+int32_t or_step(void *h, const or_limits *lim) {
+    or_solver *s = (or_solver *)h;
+    int32_t j, k = next_step(s, &j);
+    switch (k) {
+    case ST_INIT: step_init(s); break;
+    case ST_ROUND: step_round(s); break;
+    case ST_LEARN: step_learn(s, lim); break;
+    case ST_DECIDE: step_decide(s, j); break;
+    case ST_COMPLETE: step_complete(s); break;
+    case ST_GATE: step_gate(s); break;
+    default: return s->status;
+    }
+    s->last_step = k;
+    if (s->status == OR_SAT) fnv(s, 4);
+    else if (s->status == OR_UNSAT) fnv(s, 5);
+    else if (s->status == OR_UNKNOWN) fnv(s, 6);
+    return s->status;
+}
+
+/* runs up to max_steps steps (all when max_steps < 0) */
+int32_t or_run(void *h, const or_limits *lim, int64_t max_steps) {
+    or_solver *s = (or_solver *)h;
+    for (int64_t i = 0; (max_steps < 0 || i < max_steps) && s->status == OR_RUNNING; ++i)
+        or_step(s, lim);
+    return s->status;
+}
+
+/* dims: [V, A, Rh, n_static_nogoods, static_lits, W, cdl, frontier size,
+ *        n_learned, learned_lits, pending kind, pending id, status, last step,
+ *        constraints kept] */
+void or_dims(void *h, int64_t *d) {
+    or_solver *s = (or_solver *)h;
+    d[0] = s->V; d[1] = s->A; d[2] = s->Rh; d[3] = s->n0; d[4] = s->lits0;
+    d[5] = s->W; d[6] = s->cdl; d[7] = s->frontier.n; d[8] = s->n_learned;
+    d[9] = s->learned_lits; d[10] = s->pend_kind; d[11] = s->pend_id;
+    d[12] = s->status; d[13] = s->last_step; d[14] = s->Rc;
+}
+
+/* all nogoods (static then learned) as CSR */
+void or_nogoods(void *h, int32_t *off, int32_t *lits) {
+    or_solver *s = (or_solver *)h;
+    memcpy(off, s->ng_off.a, sizeof(int32_t) * (size_t)s->ng_off.n);
+    memcpy(lits, s->ng_lits.a, sizeof(int32_t) * (size_t)s->ng_lits.n);
+}
+
+void or_occ(void *h, int32_t *occ) {
+    or_solver *s = (or_solver *)h;
+    memcpy(occ, s->occ, sizeof(int32_t) * ((size_t)s->A + 1));
+}
+
+/* state: val[V+1], lvl[V+1], deps[(V+1)W], dec[cdl+1], frontier[n] */
+void or_state(void *h, int8_t *val, int32_t *lvl, uint64_t *deps, int32_t *dec,
+              int32_t *frontier) {
+    or_solver *s = (or_solver *)h;
+    size_t V1 = (size_t)s->V + 1;
+    memcpy(val, s->val, V1);
+    memcpy(lvl, s->lvl, V1 * sizeof(int32_t));
+    memcpy(deps, s->deps, V1 * s->W * sizeof(uint64_t));
+    memset(dec, 0, sizeof(int32_t) * ((size_t)s->cdl + 1));
+    for (int32_t l = 2; l <= s->cdl; ++l) dec[l] = s->dec[l];
+    memcpy(frontier, s->frontier.a, sizeof(int32_t) * (size_t)s->frontier.n);
+}
+
+void or_get_stats(void *h, or_stats *out) { *out = ((or_solver *)h)->st; }
+
+/* model over original atoms: model[p-1] = 1 iff p is true */
+void or_model(void *h, uint8_t *model) {
+    or_solver *s = (or_solver *)h;
+    for (int32_t p = 1; p <= s->A; ++p) model[p - 1] = s->val[p] == 1;
+}
+
+/* one-call solve for timing: encode, run to a verdict, copy the model */
+int32_t or_solve(int32_t n_atoms, int32_t n_rules, const int32_t *head,
+                 const int64_t *body_off, const int32_t *body_lits, int32_t W,
+                 int32_t gate_mode, const or_limits *lim, uint8_t *model,
+                 or_stats *st) {
+    int32_t err = 0;
+    void *h = or_create(n_atoms, n_rules, head, body_off, body_lits, W, gate_mode, &err);
+    if (!h) return err;
+    int32_t rc = or_run(h, lim, -1);
+    if (model && rc == OR_SAT) or_model(h, model);
+    if (st) or_get_stats(h, st);
+    or_free(h);
+    return rc;
+}

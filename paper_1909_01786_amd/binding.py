@@ -1,0 +1,350 @@
+"""Python binding of libasp (``include/asp.h``): argument marshalling only.
+
+Every step of the search runs in the HIP library; torch supplies device
+memory (the arena tensors) and streams.  There is no fallback: if
+``libasp.so`` is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libasp.so")
+
+OK, SAT, UNSAT, UNKNOWN, FIXPOINT, CONFLICT, RUNNING = 0, 1, 2, 3, 4, 5, 6
+E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_INTERNAL, E_TIMEOUT = -1, -2, -3, -4, -5, -6
+STEP_NONE, STEP_INIT, STEP_ROUND, STEP_LEARN, STEP_DECIDE, STEP_COMPLETE, STEP_GATE, STEP_DONE = range(8)
+GATE_UNFOUNDED, GATE_ALLDEC = 0, 1
+
+
+class AspError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{asp_status_str(status)} ({status}): {msg}")
+        self.status = status
+
+
+class asp_options(C.Structure):
+    _fields_ = [("W", C.c_int32), ("gate", C.c_int32), ("learned_cap_ng", C.c_int64),
+                ("learned_cap_lits", C.c_int64)]
+
+
+class asp_limits(C.Structure):
+    _fields_ = [("max_conflicts", C.c_int64), ("max_ms", C.c_int64)]
+
+
+class asp_schedule(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("wg_per_cu", C.c_int32)]
+
+
+_STAT_NAMES = ("rounds", "visits", "literal_checks", "propagations", "decisions", "conflicts",
+               "learned", "learned_len", "gate_failures", "completes")
+
+
+class asp_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in _STAT_NAMES] + [
+        ("trace_hash", C.c_uint64), ("status", C.c_int32), ("last_step", C.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class asp_sizes(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("n_rules_headed", C.c_int32),
+                ("n_constraints", C.c_int32), ("n_vars", C.c_int32), ("n_nogoods", C.c_int64),
+                ("n_lits", C.c_int64), ("n_units", C.c_int64), ("device_bytes", C.c_uint64)]
+
+
+class asp_prop_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("conflict_id", C.c_int32), ("rounds", C.c_int64),
+                ("implied", C.c_int64), ("visits", C.c_int64), ("literal_checks", C.c_int64)]
+
+
+class asp_state(C.Structure):
+    _fields_ = [("n_vars", C.c_int32), ("W", C.c_int32), ("cdl", C.c_int32),
+                ("frontier_len", C.c_int32), ("n_learned", C.c_int32), ("pending", C.c_int32),
+                ("learned_lits", C.c_int64), ("initialised", C.c_int32), ("status", C.c_int32),
+                ("val", C.c_void_p), ("lvl", C.c_void_p), ("deps", C.c_void_p),
+                ("dec", C.c_void_p), ("frontier", C.c_void_p), ("learned_off", C.c_void_p),
+                ("learned", C.c_void_p), ("stats", asp_stats)]
+
+
+EXPORTS = (
+    "asp_load_program", "asp_free_program", "asp_program_nogoods", "asp_bind_device",
+    "asp_propagate", "asp_analyze_conflict", "asp_run_steps", "asp_solve",
+    "asp_state_export", "asp_state_import", "asp_batch_create", "asp_batch_bind",
+    "asp_solve_batch", "asp_batch_results", "asp_batch_last_ms", "asp_batch_free",
+    "asp_status_str", "asp_last_error",
+)
+
+_lib = None
+
+
+def lib():
+    """Load libasp.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1909_01786_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+        sig = {
+            "asp_load_program": (i32, [i32, i32, P, P, P, C.POINTER(asp_options), C.POINTER(P),
+                                       C.POINTER(asp_sizes)]),
+            "asp_free_program": (i32, [P]),
+            "asp_program_nogoods": (i32, [P, P, P]),
+            "asp_bind_device": (i32, [P, P, u64, P, C.POINTER(asp_schedule)]),
+            "asp_propagate": (i32, [P, P, i32, C.POINTER(asp_prop_result)]),
+            "asp_analyze_conflict": (i32, [P, P, C.POINTER(asp_limits), P, i32, C.POINTER(i32),
+                                           C.POINTER(i32)]),
+            "asp_run_steps": (i32, [P, P, C.POINTER(asp_limits), i64, C.POINTER(asp_stats)]),
+            "asp_solve": (i32, [P, P, C.POINTER(asp_limits), P, C.POINTER(asp_stats)]),
+            "asp_state_export": (i32, [P, P, C.POINTER(asp_state)]),
+            "asp_state_import": (i32, [P, P, C.POINTER(asp_state)]),
+            "asp_batch_create": (i32, [i32, P, C.POINTER(asp_schedule), C.POINTER(P),
+                                       C.POINTER(u64), C.POINTER(u64)]),
+            "asp_batch_bind": (i32, [P, P, u64, P]),
+            "asp_solve_batch": (i32, [P, P, C.POINTER(asp_limits)]),
+            "asp_batch_results": (i32, [P, P, P, P, P]),
+            "asp_batch_last_ms": (i32, [P, C.POINTER(C.c_double)]),
+            "asp_batch_free": (i32, [P]),
+            "asp_status_str": (C.c_char_p, [i32]),
+            "asp_last_error": (i32, [C.c_char_p, u64]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def asp_status_str(st: int) -> str:
+    return lib().asp_status_str(int(st)).decode()
+
+
+def last_error() -> str:
+    buf = C.create_string_buffer(1024)
+    lib().asp_last_error(buf, 1024)
+    return buf.value.decode(errors="replace")
+
+
+def _check(rc: int, allowed=()) -> int:
+    if rc < 0 and rc not in allowed:
+        raise AspError(rc, last_error())
+    return rc
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p) if a is not None and a.size else None
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _arena(nbytes: int, device):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def limits(max_conflicts: int = -1, max_ms: int = 0) -> asp_limits:
+    return asp_limits(int(max_conflicts), int(max_ms))
+
+
+def options(W: int = 1, gate: int = GATE_UNFOUNDED, learned_cap_ng: int = 1 << 20,
+            learned_cap_lits: int = 1 << 22) -> asp_options:
+    return asp_options(int(W), int(gate), int(learned_cap_ng), int(learned_cap_lits))
+
+
+@dataclass
+class State:
+    n_vars: int
+    W: int
+    cdl: int
+    val: np.ndarray
+    lvl: np.ndarray
+    deps: np.ndarray
+    dec: np.ndarray
+    frontier: np.ndarray
+    learned_off: np.ndarray
+    learned: np.ndarray
+    pending: int
+    initialised: int
+    status: int
+    stats: dict
+
+
+class Program:
+    """A ground program encoded by libasp (asp_load_program)."""
+
+    def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED,
+                 learned_cap_ng: int = 1 << 20, learned_cap_lits: int = 1 << 22):
+        self._head = np.ascontiguousarray(prog.head, np.int32)
+        self._off = np.ascontiguousarray(prog.body_off, np.int64)
+        self._lits = np.ascontiguousarray(prog.body_lits, np.int32)
+        self.opt = options(W, gate, learned_cap_ng, learned_cap_lits)
+        self.sizes = asp_sizes()
+        h = C.c_void_p()
+        _check(lib().asp_load_program(int(prog.n_atoms), int(self._head.shape[0]),
+                                      _ptr(self._head), _ptr(self._off), _ptr(self._lits),
+                                      C.byref(self.opt), C.byref(h), C.byref(self.sizes)))
+        self._h = h
+        self.n_atoms = int(prog.n_atoms)
+        self.W = int(W)
+        self.arena = None
+        self.stream = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and h.value and _lib is not None:
+            _lib.asp_free_program(h)
+            self._h = None
+
+    @property
+    def n_vars(self) -> int:
+        return int(self.sizes.n_vars)
+
+    def nogoods(self):
+        n = int(self.sizes.n_nogoods)
+        off = np.zeros(n + 1, np.int32)
+        lits = np.zeros(max(int(self.sizes.n_lits), 1), np.int32)
+        _check(lib().asp_program_nogoods(self._h, _ptr(off), _ptr(lits)))
+        return off, lits[:int(self.sizes.n_lits)]
+
+    def bind(self, device="cuda", threads: int = 256, stream=None):
+        """Allocate the arena (torch) and upload the program."""
+        self.arena = _arena(self.sizes.device_bytes, device)
+        self.stream = stream
+        sch = asp_schedule(int(threads), 1)
+        _check(lib().asp_bind_device(self._h, C.c_void_p(self.arena.data_ptr()),
+                                     int(self.arena.numel()), _stream_ptr(stream), C.byref(sch)))
+        return self
+
+    def propagate(self, max_rounds: int = 0):
+        r = asp_prop_result()
+        st = _check(lib().asp_propagate(self._h, _stream_ptr(self.stream), int(max_rounds),
+                                        C.byref(r)))
+        return st, {n: getattr(r, n) for n, _ in r._fields_}
+
+    def analyze_conflict(self, lim: asp_limits | None = None, cap: int = 1 << 16):
+        buf = np.zeros(cap, np.int32)
+        ln, bj = C.c_int32(0), C.c_int32(0)
+        st = _check(lib().asp_analyze_conflict(self._h, _stream_ptr(self.stream),
+                                               C.byref(lim) if lim else None, _ptr(buf), cap,
+                                               C.byref(ln), C.byref(bj)))
+        return st, buf[:ln.value].copy(), bj.value
+
+    def run_steps(self, n_steps: int, lim: asp_limits | None = None):
+        s = asp_stats()
+        st = _check(lib().asp_run_steps(self._h, _stream_ptr(self.stream),
+                                        C.byref(lim) if lim else None, int(n_steps), C.byref(s)))
+        return st, s.as_dict()
+
+    def solve(self, lim: asp_limits | None = None):
+        m = np.zeros(max(self.n_atoms, 1), np.uint8)
+        s = asp_stats()
+        st = _check(lib().asp_solve(self._h, _stream_ptr(self.stream),
+                                    C.byref(lim) if lim else None, _ptr(m), C.byref(s)))
+        return st, (m[:self.n_atoms].copy() if st == SAT else None), s.as_dict()
+
+    def export_state(self) -> State:
+        st = asp_state()
+        _check(lib().asp_state_export(self._h, _stream_ptr(self.stream), C.byref(st)))
+        V, W = st.n_vars, st.W
+        val = np.zeros(V + 1, np.int8)
+        lvl = np.zeros(V + 1, np.int32)
+        deps = np.zeros((V + 1) * W, np.uint64)
+        dec = np.zeros(st.cdl + 1, np.int32)
+        fr = np.zeros(max(st.frontier_len, 1), np.int32)
+        loff = np.zeros(st.n_learned + 1, np.int32)
+        lits = np.zeros(max(st.learned_lits, 1), np.int32)
+        st.val, st.lvl, st.deps, st.dec = _ptr(val), _ptr(lvl), _ptr(deps), _ptr(dec)
+        st.frontier, st.learned_off, st.learned = _ptr(fr), _ptr(loff), _ptr(lits)
+        _check(lib().asp_state_export(self._h, _stream_ptr(self.stream), C.byref(st)))
+        return State(V, W, st.cdl, val, lvl, deps.reshape(V + 1, W), dec,
+                     fr[:st.frontier_len], loff, lits[:st.learned_lits], st.pending,
+                     st.initialised, st.status, st.stats.as_dict())
+
+    def import_state(self, s: State):
+        st = asp_state()
+        val = np.ascontiguousarray(s.val, np.int8)
+        lvl = np.ascontiguousarray(s.lvl, np.int32)
+        deps = np.ascontiguousarray(np.asarray(s.deps, np.uint64).reshape(-1))
+        dec = np.ascontiguousarray(s.dec, np.int32)
+        fr = np.ascontiguousarray(s.frontier, np.int32)
+        loff = np.ascontiguousarray(s.learned_off, np.int32)
+        lits = np.ascontiguousarray(s.learned, np.int32)
+        st.n_vars, st.W, st.cdl = int(s.n_vars), int(s.W), int(s.cdl)
+        st.frontier_len = int(fr.shape[0])
+        st.n_learned = int(loff.shape[0]) - 1
+        st.pending = int(s.pending)
+        st.learned_lits = int(lits.shape[0])
+        st.initialised = int(s.initialised)
+        st.status = RUNNING
+        st.val, st.lvl, st.deps, st.dec = _ptr(val), _ptr(lvl), _ptr(deps), _ptr(dec)
+        st.frontier, st.learned_off, st.learned = _ptr(fr), _ptr(loff), _ptr(lits)
+        for k, v in (s.stats or {}).items():
+            if hasattr(st.stats, k):
+                setattr(st.stats, k, int(v))
+        _check(lib().asp_state_import(self._h, _stream_ptr(self.stream), C.byref(st)))
+
+
+class Batch:
+    """Many programs solved by one persistent launch (asp_solve_batch)."""
+
+    def __init__(self, programs, threads: int = 64, wg_per_cu: int = 8):
+        self.programs = list(programs)
+        arr = (C.c_void_p * len(self.programs))(*[p._h.value for p in self.programs])
+        self._arr = arr
+        sch = asp_schedule(int(threads), int(wg_per_cu))
+        h = C.c_void_p()
+        nb, mb = C.c_uint64(0), C.c_uint64(0)
+        _check(lib().asp_batch_create(len(self.programs), C.cast(arr, C.c_void_p), C.byref(sch),
+                                      C.byref(h), C.byref(nb), C.byref(mb)))
+        self._h = h
+        self.device_bytes = int(nb.value)
+        self.model_bytes = int(mb.value)
+        self.arena = None
+        self.stream = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and h.value and _lib is not None:
+            _lib.asp_batch_free(h)
+            self._h = None
+
+    def bind(self, device="cuda", stream=None):
+        self.arena = _arena(self.device_bytes, device)
+        self.stream = stream
+        _check(lib().asp_batch_bind(self._h, C.c_void_p(self.arena.data_ptr()),
+                                    int(self.arena.numel()), _stream_ptr(stream)))
+        return self
+
+    def solve(self, lim: asp_limits | None = None):
+        """Enqueue the batched solve on the stream (asynchronous)."""
+        _check(lib().asp_solve_batch(self._h, _stream_ptr(self.stream),
+                                     C.byref(lim) if lim else None))
+
+    def last_ms(self) -> float:
+        ms = C.c_double(0)
+        _check(lib().asp_batch_last_ms(self._h, C.byref(ms)))
+        return float(ms.value)
+
+    def results(self):
+        n = len(self.programs)
+        verd = np.zeros(n, np.int32)
+        models = np.zeros(max(self.model_bytes, 1), np.uint8)
+        stats = (asp_stats * n)()
+        _check(lib().asp_batch_results(self._h, _stream_ptr(self.stream), _ptr(verd),
+                                       _ptr(models), C.cast(stats, C.c_void_p)))
+        out_models, o = [], 0
+        for p in self.programs:
+            out_models.append(models[o:o + p.n_atoms].copy())
+            o += p.n_atoms
+        return verd, out_models, [s.as_dict() for s in stats]

@@ -1,0 +1,866 @@
+// api.cpp -- C ABI of libasp (declared in include/asp.h).
+//
+// Host side: validates and encodes programs (encode.cpp), plans the device
+// arena, uploads the static tables, launches the search kernels
+// (solver.hip) and moves states and results.  Device memory is always the
+// caller's; nothing here allocates on the device.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/asp.h"
+#include "encode.h"
+#include "layout.h"
+
+namespace asp {
+size_t lds_bytes(int threads, int words);
+hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s);
+hipError_t launch_reset_queue(int32_t* q, hipStream_t s);
+hipError_t set_max_lds(int threads, size_t lds);
+hipError_t occupancy(int threads, size_t lds, int* blocks_per_cu);
+}  // namespace asp
+
+using namespace asp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(ASP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct DeviceInfo {
+    int ok = 0;
+    int cus = 0;
+    size_t max_lds = 0;
+    int clock_khz = 0;  // wall clock rate
+};
+
+DeviceInfo device_info() {
+    DeviceInfo d;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return d;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return d;
+    d.cus = p.multiProcessorCount;
+    d.max_lds = p.sharedMemPerBlock;
+    int rate = 0;
+    if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess)
+        d.clock_khz = rate;
+    d.ok = d.cus > 0;
+    return d;
+}
+
+bool valid_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- handles
+struct Plan {
+    int32_t n = 0, threads = 256, grid = 1, W = 1, gate = 0;
+    int64_t Vmax = 0, Rhmax = 0, cap_ng = 0, cap_lits = 0;
+    int32_t words = 1;
+    size_t lds = 0;
+    SlotLayout lay{};
+    uint64_t off_desc = 0, off_order = 0, off_ngo = 0, off_ngl = 0, off_mo = 0, off_mi = 0,
+             off_rh = 0, off_ro = 0, off_rbo = 0, off_rbl = 0, off_verd = 0, off_stats = 0,
+             off_models = 0, off_queue = 0, off_slots = 0, total = 0;
+    std::vector<InstDesc> desc;
+    std::vector<int32_t> order;
+    int64_t tot_ngo = 0, tot_ngl = 0, tot_mo = 0, tot_mi = 0, tot_rules = 0, tot_rbo = 0,
+            tot_rbl = 0, tot_model = 0;
+};
+
+struct asp_program {
+    HostProgram hp;
+    asp_options opt{};
+    // single-instance binding
+    bool bound = false;
+    uint8_t* arena = nullptr;
+    uint64_t bytes = 0;
+    Plan plan;
+    int32_t threads = 256;
+};
+
+struct asp_batch {
+    std::vector<const HostProgram*> progs;
+    asp_options opt{};
+    Plan plan;
+    bool bound = false;
+    uint8_t* arena = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+};
+
+namespace {
+
+asp_options default_options() {
+    asp_options o;
+    o.W = 1;
+    o.gate = ASP_GATE_UNFOUNDED;
+    o.learned_cap_ng = 1 << 20;
+    o.learned_cap_lits = 1 << 22;
+    return o;
+}
+
+void slot_layout(Plan& P) {
+    SlotLayout& L = P.lay;
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t at = o;
+        o = align_up(o + bytes);
+        return (int64_t)at;
+    };
+    const uint64_t V1 = (uint64_t)P.Vmax + 1, R3 = (uint64_t)P.Rhmax + 3;
+    L.ctrl = take(sizeof(SlotCtrl));
+    L.val8 = take(V1);
+    L.lvl = take(4 * V1);
+    L.deps = take(8 * V1 * (uint64_t)P.W);
+    L.win = take(4 * V1);
+    L.trail = take(4 * V1);
+    L.tlim = take(4 * R3);
+    L.dec = take(4 * R3);
+    L.locc_ptr = take(8 * V1);
+    L.locc_n = take(8 * V1);
+    L.locc_cap = take(8 * V1);
+    L.l_off = take(4 * ((uint64_t)P.cap_ng + 1));
+    L.l_lits = take(4 * (uint64_t)P.cap_lits);
+    // doubling occurrence arrays: every list of n entries has used at most
+    // 4n + 8 entries; learned nogoods hold only decision literals T b_r, so
+    // at most Rh lists exist
+    L.pool_cap = 4 * P.cap_lits + 8 * (P.Rhmax + 1);
+    L.pool = take(4 * (uint64_t)L.pool_cap);
+    L.stride = (int64_t)o;
+}
+
+int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_options& opt,
+                  int32_t threads, int32_t grid, Plan& P) {
+    P = Plan();
+    P.n = (int32_t)progs.size();
+    P.threads = threads;
+    P.W = opt.W;
+    P.gate = opt.gate;
+    P.cap_ng = opt.learned_cap_ng;
+    P.cap_lits = opt.learned_cap_lits;
+    P.desc.resize(P.n);
+    for (int32_t i = 0; i < P.n; ++i) {
+        const HostProgram& h = *progs[i];
+        InstDesc& d = P.desc[i];
+        d.ng_off = P.tot_ngo;
+        d.ng_lits = P.tot_ngl;
+        d.map_off = P.tot_mo;
+        d.map_ids = P.tot_mi;
+        d.rules = P.tot_rules;
+        d.rb_off = P.tot_rbo;
+        d.rb_lits = P.tot_rbl;
+        d.model = P.tot_model;
+        d.A = h.A;
+        d.Rh = h.Rh;
+        d.V = h.V;
+        d.n_static = (int32_t)h.n_nogoods();
+        d.u0 = h.u0;
+        d.u1 = h.u1;
+        d.has_empty = h.has_empty;
+        d.pad = 0;
+        if ((int64_t)h.n_nogoods() + P.cap_ng >= ((int64_t)1 << 30))
+            return fail(ASP_E_CAPACITY, "nogood ids beyond 2^30");
+        P.tot_ngo += (int64_t)h.ng_off.size();
+        P.tot_ngl += (int64_t)h.ng_lits.size();
+        P.tot_mo += (int64_t)h.map_off.size();
+        P.tot_mi += (int64_t)h.map_ids.size();
+        P.tot_rules += (int64_t)h.rule_head.size();
+        P.tot_rbo += (int64_t)h.rb_off.size();
+        P.tot_rbl += (int64_t)h.rb_lits.size();
+        P.tot_model += h.A;
+        P.Vmax = std::max<int64_t>(P.Vmax, h.V);
+        P.Rhmax = std::max<int64_t>(P.Rhmax, h.Rh);
+    }
+    P.order.resize(P.n);
+    std::iota(P.order.begin(), P.order.end(), 0);
+    std::stable_sort(P.order.begin(), P.order.end(), [&](int32_t a, int32_t b) {
+        const HostProgram& x = *progs[a];
+        const HostProgram& y = *progs[b];
+        return x.ng_lits.size() + (size_t)x.V > y.ng_lits.size() + (size_t)y.V;
+    });
+    P.grid = std::max(1, std::min(grid, std::max(P.n, 1)));
+    P.words = (int32_t)((P.Vmax + 1 + 15) / 16);
+    P.lds = lds_bytes(threads, P.words);
+    slot_layout(P);
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    P.off_desc = take(sizeof(InstDesc) * (uint64_t)P.n);
+    P.off_order = take(4 * (uint64_t)P.n);
+    P.off_ngo = take(4 * (uint64_t)P.tot_ngo);
+    P.off_ngl = take(4 * (uint64_t)P.tot_ngl);
+    P.off_mo = take(4 * (uint64_t)P.tot_mo);
+    P.off_mi = take(4 * (uint64_t)P.tot_mi);
+    P.off_rh = take(4 * (uint64_t)P.tot_rules);
+    P.off_ro = take(4 * (uint64_t)P.tot_rules);
+    P.off_rbo = take(4 * (uint64_t)P.tot_rbo);
+    P.off_rbl = take(4 * (uint64_t)P.tot_rbl);
+    P.off_verd = take(4 * (uint64_t)P.n);
+    P.off_stats = take(sizeof(DevStats) * (uint64_t)P.n);
+    P.off_models = take((uint64_t)P.tot_model + 1);
+    P.off_queue = take(64);
+    P.off_slots = take((uint64_t)P.lay.stride * (uint64_t)P.grid);
+    P.total = o;
+    return ASP_OK;
+}
+
+template <class T>
+std::vector<T> concat(const std::vector<const HostProgram*>& progs,
+                      const std::vector<T> HostProgram::*field) {
+    size_t n = 0;
+    for (auto* p : progs) n += (p->*field).size();
+    std::vector<T> out;
+    out.reserve(n);
+    for (auto* p : progs) out.insert(out.end(), (p->*field).begin(), (p->*field).end());
+    return out;
+}
+
+int32_t upload_static(const std::vector<const HostProgram*>& progs, const Plan& P,
+                      uint8_t* arena, hipStream_t s) {
+    auto put = [&](uint64_t off, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(arena + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    std::vector<int32_t> ngo = concat(progs, &HostProgram::ng_off);
+    std::vector<int32_t> ngl = concat(progs, &HostProgram::ng_lits);
+    std::vector<int32_t> mo = concat(progs, &HostProgram::map_off);
+    std::vector<int32_t> mi = concat(progs, &HostProgram::map_ids);
+    std::vector<int32_t> rh = concat(progs, &HostProgram::rule_head);
+    std::vector<int32_t> ro = concat(progs, &HostProgram::rule_occ);
+    std::vector<int32_t> rbo = concat(progs, &HostProgram::rb_off);
+    std::vector<int32_t> rbl = concat(progs, &HostProgram::rb_lits);
+    HIPCHK(put(P.off_desc, P.desc.data(), sizeof(InstDesc) * P.desc.size()));
+    HIPCHK(put(P.off_order, P.order.data(), 4 * P.order.size()));
+    HIPCHK(put(P.off_ngo, ngo.data(), 4 * ngo.size()));
+    HIPCHK(put(P.off_ngl, ngl.data(), 4 * ngl.size()));
+    HIPCHK(put(P.off_mo, mo.data(), 4 * mo.size()));
+    HIPCHK(put(P.off_mi, mi.data(), 4 * mi.size()));
+    HIPCHK(put(P.off_rh, rh.data(), 4 * rh.size()));
+    HIPCHK(put(P.off_ro, ro.data(), 4 * ro.size()));
+    HIPCHK(put(P.off_rbo, rbo.data(), 4 * rbo.size()));
+    HIPCHK(put(P.off_rbl, rbl.data(), 4 * rbl.size()));
+    HIPCHK(hipStreamSynchronize(s));  // host staging vectors die here
+    return ASP_OK;
+}
+
+KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode) {
+    KArgs a{};
+    a.inst = (const InstDesc*)(arena + P.off_desc);
+    a.order = (const int32_t*)(arena + P.off_order);
+    a.n_inst = P.n;
+    a.mode = mode;
+    a.ng_off = (const int32_t*)(arena + P.off_ngo);
+    a.ng_lits = (const int32_t*)(arena + P.off_ngl);
+    a.map_off = (const int32_t*)(arena + P.off_mo);
+    a.map_ids = (const int32_t*)(arena + P.off_mi);
+    a.rule_head = (const int32_t*)(arena + P.off_rh);
+    a.rule_occ = (const int32_t*)(arena + P.off_ro);
+    a.rb_off = (const int32_t*)(arena + P.off_rbo);
+    a.rb_lits = (const int32_t*)(arena + P.off_rbl);
+    a.slots = arena + P.off_slots;
+    a.lay = P.lay;
+    a.queue = (int32_t*)(arena + P.off_queue);
+    a.verdicts = (int32_t*)(arena + P.off_verd);
+    a.stats = (DevStats*)(arena + P.off_stats);
+    a.models = arena + P.off_models;
+    a.W = P.W;
+    a.gate_mode = P.gate;
+    a.words = P.words;
+    a.step_mask = 0;
+    a.max_steps = -1;
+    a.max_conflicts = -1;
+    a.cap_ng = P.cap_ng;
+    a.cap_lits = P.cap_lits;
+    a.max_ticks = 0;
+    return a;
+}
+
+// Device wall-clock guard used when the caller gives none: every launch ends.
+constexpr int64_t kDefaultMaxMs = 600000;
+
+void apply_limits(KArgs& a, const Plan& P, const asp_limits* lim, const DeviceInfo& di) {
+    a.max_conflicts = lim ? lim->max_conflicts : -1;
+    int64_t ms = (lim && lim->max_ms > 0) ? lim->max_ms : kDefaultMaxMs;
+    a.max_ticks = di.clock_khz > 0 ? (uint64_t)ms * (uint64_t)di.clock_khz : 0;
+    // step guard: between two conflicts a search runs at most 3V + 4 steps
+    if (a.max_conflicts >= 0)
+        a.max_steps = (a.max_conflicts + 2) * (3 * P.Vmax + P.Rhmax + 16) + 16;
+    else
+        a.max_steps = -1;
+}
+
+void to_stats(const DevStats& d, asp_stats* s) {
+    s->rounds = d.rounds;
+    s->visits = d.visits;
+    s->literal_checks = d.checks;
+    s->propagations = d.props;
+    s->decisions = d.decisions;
+    s->conflicts = d.conflicts;
+    s->learned = d.learned;
+    s->learned_len = d.learned_len;
+    s->gate_failures = d.gate_fail;
+    s->completes = d.completes;
+    s->trace_hash = d.hash;
+    s->status = d.status;
+    s->last_step = d.last_step;
+}
+
+void ctrl_stats(const SlotCtrl& k, asp_stats* s) {
+    s->rounds = k.rounds;
+    s->visits = k.visits;
+    s->literal_checks = k.checks;
+    s->propagations = k.props;
+    s->decisions = k.decisions;
+    s->conflicts = k.conflicts;
+    s->learned = k.learned;
+    s->learned_len = k.learned_len;
+    s->gate_failures = k.gate_fail;
+    s->completes = k.completes;
+    s->trace_hash = k.hash;
+    s->status = k.status;
+    s->last_step = k.last_step;
+}
+
+int32_t check_launch(const Plan& P, const DeviceInfo& di) {
+    if (!di.ok) return fail(ASP_E_DEVICE, "no HIP device");
+    if (P.lds > di.max_lds)
+        return fail(ASP_E_CAPACITY, "largest instance needs " + std::to_string(P.lds) +
+                                        " bytes of LDS, device allows " +
+                                        std::to_string(di.max_lds));
+    (void)set_max_lds(P.threads, P.lds);  // best effort: older runtimes ignore it
+    return ASP_OK;
+}
+
+// single program: run the step kernel on slot 0
+int32_t run_single(asp_program* p, hipStream_t s, int32_t mode, int32_t mask, int64_t steps,
+                   const asp_limits* lim) {
+    DeviceInfo di = device_info();
+    int32_t rc = check_launch(p->plan, di);
+    if (rc) return rc;
+    KArgs a = make_args(p->plan, p->arena, mode);
+    apply_limits(a, p->plan, lim, di);
+    a.step_mask = mask;
+    a.max_steps = steps;
+    HIPCHK(launch_search(a, p->threads, 1, p->plan.lds, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ASP_OK;
+}
+
+SlotCtrl* ctrl_ptr(asp_program* p) { return (SlotCtrl*)(p->arena + p->plan.off_slots + p->plan.lay.ctrl); }
+
+int32_t read_ctrl(asp_program* p, hipStream_t s, SlotCtrl* out) {
+    HIPCHK(hipMemcpyAsync(out, ctrl_ptr(p), sizeof(SlotCtrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ASP_OK;
+}
+
+template <class T>
+T* slot_arr(asp_program* p, int64_t off) {
+    return (T*)(p->arena + p->plan.off_slots + off);
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+extern "C" {
+
+const char* asp_status_str(int32_t st) {
+    switch (st) {
+    case ASP_OK: return "ok";
+    case ASP_SAT: return "sat";
+    case ASP_UNSAT: return "unsat";
+    case ASP_UNKNOWN: return "unknown";
+    case ASP_FIXPOINT: return "fixpoint";
+    case ASP_CONFLICT: return "conflict";
+    case ASP_RUNNING: return "running";
+    case ASP_E_INVALID: return "invalid input";
+    case ASP_E_CAPACITY: return "capacity exceeded";
+    case ASP_E_DEVICE: return "device error";
+    case ASP_E_STATE: return "wrong call order";
+    case ASP_E_INTERNAL: return "internal error";
+    case ASP_E_TIMEOUT: return "device time limit";
+    default: return "unknown status";
+    }
+}
+
+int32_t asp_last_error(char* buf, uint64_t len) {
+    if (!buf || len == 0) return ASP_E_INVALID;
+    size_t n = std::min<size_t>(g_err.size(), (size_t)len - 1);
+    memcpy(buf, g_err.data(), n);
+    buf[n] = 0;
+    return ASP_OK;
+}
+
+int32_t asp_load_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
+                         const int64_t* body_off, const int32_t* body_lits,
+                         const asp_options* opt, asp_program** out, asp_sizes* sizes) {
+    if (!out) return fail(ASP_E_INVALID, "null output handle");
+    *out = nullptr;
+    asp_options o = opt ? *opt : default_options();
+    if (o.W < 1 || o.W > kMaxW) return fail(ASP_E_INVALID, "W must be in 1..64");
+    if (o.gate != ASP_GATE_UNFOUNDED && o.gate != ASP_GATE_ALLDEC)
+        return fail(ASP_E_INVALID, "unknown gate option");
+    if (o.learned_cap_ng < 1 || o.learned_cap_lits < 1 || o.learned_cap_ng > (1 << 29) ||
+        o.learned_cap_lits > ((int64_t)1 << 29))
+        return fail(ASP_E_INVALID, "learned capacities must be in 1..2^29");
+    std::unique_ptr<asp_program> p(new asp_program());
+    std::string err;
+    int rc = encode_program(n_atoms, n_rules, head, body_off, body_lits, &p->hp, &err);
+    if (rc) return fail(ASP_E_INVALID, err);
+    p->opt = o;
+    std::vector<const HostProgram*> one{&p->hp};
+    rc = make_plan(one, o, 256, 1, p->plan);
+    if (rc) return rc;
+    if (sizes) {
+        sizes->n_atoms = p->hp.A;
+        sizes->n_rules_headed = p->hp.Rh;
+        sizes->n_constraints = p->hp.Rc;
+        sizes->n_vars = p->hp.V;
+        sizes->n_nogoods = p->hp.n_nogoods();
+        sizes->n_lits = (int64_t)p->hp.ng_lits.size();
+        sizes->n_units = p->hp.u1 - p->hp.u0;
+        sizes->device_bytes = p->plan.total;
+    }
+    *out = p.release();
+    return ASP_OK;
+}
+
+int32_t asp_free_program(asp_program* prog) {
+    delete prog;
+    return ASP_OK;
+}
+
+int32_t asp_program_nogoods(const asp_program* p, int32_t* off, int32_t* lits) {
+    if (!p) return fail(ASP_E_INVALID, "null program");
+    if (off) memcpy(off, p->hp.ng_off.data(), 4 * p->hp.ng_off.size());
+    if (lits && !p->hp.ng_lits.empty()) memcpy(lits, p->hp.ng_lits.data(), 4 * p->hp.ng_lits.size());
+    return ASP_OK;
+}
+
+int32_t asp_bind_device(asp_program* p, void* dev_arena, uint64_t bytes, void* stream,
+                        const asp_schedule* sched) {
+    if (!p || !dev_arena) return fail(ASP_E_INVALID, "null program or arena");
+    if ((uintptr_t)dev_arena % kAlign) return fail(ASP_E_INVALID, "arena must be 256-byte aligned");
+    int32_t threads = sched ? sched->threads : 256;
+    if (!valid_threads(threads)) return fail(ASP_E_INVALID, "threads must be 64..1024, power of 2");
+    std::vector<const HostProgram*> one{&p->hp};
+    Plan P;
+    int32_t rc = make_plan(one, p->opt, threads, 1, P);
+    if (rc) return rc;
+    if (bytes < P.total)
+        return fail(ASP_E_CAPACITY, "arena of " + std::to_string(bytes) + " bytes, need " +
+                                        std::to_string(P.total));
+    hipStream_t s = (hipStream_t)stream;
+    p->bound = false;
+    p->plan = P;
+    p->arena = (uint8_t*)dev_arena;
+    p->bytes = bytes;
+    p->threads = threads;
+    rc = upload_static(one, P, p->arena, s);
+    if (rc) return rc;
+    rc = run_single(p, s, MODE_RESET, 0, 0, nullptr);
+    if (rc) return rc;
+    p->bound = true;
+    return ASP_OK;
+}
+
+int32_t asp_propagate(asp_program* p, void* stream, int32_t max_rounds, asp_prop_result* out) {
+    if (!p || !p->bound) return fail(ASP_E_STATE, "program not bound to a device arena");
+    hipStream_t s = (hipStream_t)stream;
+    SlotCtrl b, e;
+    int32_t rc = read_ctrl(p, s, &b);
+    if (rc) return rc;
+    if (b.status != ASP_RUNNING) return b.status;
+    int64_t steps = max_rounds > 0 ? (int64_t)max_rounds + (b.init_done ? 0 : 1) : INT64_MAX;
+    rc = run_single(p, s, MODE_STEPS, (1 << STEP_INIT) | (1 << STEP_ROUND), steps, nullptr);
+    if (rc) return rc;
+    rc = read_ctrl(p, s, &e);
+    if (rc) return rc;
+    int32_t st;
+    if (e.status != ASP_RUNNING) st = e.status;
+    else if (e.pend_kind == 1) st = ASP_CONFLICT;
+    else if (e.qt == e.qh) st = ASP_FIXPOINT;
+    else st = ASP_RUNNING;
+    if (out) {
+        out->status = st;
+        out->conflict_id = e.pend_kind == 1 ? e.pending : -1;
+        out->rounds = e.rounds - b.rounds;
+        out->implied = e.props - b.props;
+        out->visits = e.visits - b.visits;
+        out->literal_checks = e.checks - b.checks;
+    }
+    return st;
+}
+
+int32_t asp_analyze_conflict(asp_program* p, void* stream, const asp_limits* lim,
+                             int32_t* learned_lits, int32_t cap, int32_t* learned_len,
+                             int32_t* backjump_level) {
+    if (!p || !p->bound) return fail(ASP_E_STATE, "program not bound to a device arena");
+    hipStream_t s = (hipStream_t)stream;
+    SlotCtrl b, e;
+    int32_t rc = read_ctrl(p, s, &b);
+    if (rc) return rc;
+    if (b.status != ASP_RUNNING || b.pend_kind != 1)
+        return fail(ASP_E_STATE, "no pending propagation conflict");
+    rc = run_single(p, s, MODE_STEPS, 1 << STEP_LEARN, 1, lim);
+    if (rc) return rc;
+    rc = read_ctrl(p, s, &e);
+    if (rc) return rc;
+    if (e.status != ASP_RUNNING) return e.status;
+    if (e.status == ASP_RUNNING && e.pend_kind != 0) return fail(ASP_E_INTERNAL, "learning did not run");
+    int32_t off[2];
+    HIPCHK(hipMemcpyAsync(off, slot_arr<int32_t>(p, p->plan.lay.l_off) + (e.n_learned - 1), 8,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int32_t len = off[1] - off[0];
+    if (learned_len) *learned_len = len;
+    if (backjump_level) *backjump_level = e.cdl;
+    if (learned_lits) {
+        if (cap < len) return fail(ASP_E_CAPACITY, "learned nogood longer than cap");
+        HIPCHK(hipMemcpyAsync(learned_lits, slot_arr<int32_t>(p, p->plan.lay.l_lits) + off[0],
+                              4 * (size_t)len, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return ASP_OK;
+}
+
+int32_t asp_run_steps(asp_program* p, void* stream, const asp_limits* lim, int64_t n_steps,
+                      asp_stats* stats) {
+    if (!p || !p->bound) return fail(ASP_E_STATE, "program not bound to a device arena");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t rc = run_single(p, s, MODE_STEPS, 0xff, n_steps < 0 ? INT64_MAX : n_steps, lim);
+    if (rc) return rc;
+    SlotCtrl e;
+    rc = read_ctrl(p, s, &e);
+    if (rc) return rc;
+    if (stats) ctrl_stats(e, stats);
+    return e.status;
+}
+
+int32_t asp_solve(asp_program* p, void* stream, const asp_limits* lim, uint8_t* model,
+                  asp_stats* stats) {
+    if (!p || !p->bound) return fail(ASP_E_STATE, "program not bound to a device arena");
+    hipStream_t s = (hipStream_t)stream;
+    DeviceInfo di = device_info();
+    int32_t rc = check_launch(p->plan, di);
+    if (rc) return rc;
+    KArgs a = make_args(p->plan, p->arena, MODE_SOLVE);
+    apply_limits(a, p->plan, lim, di);
+    HIPCHK(launch_reset_queue(a.queue, s));
+    HIPCHK(launch_search(a, p->threads, 1, p->plan.lds, s));
+    DevStats d;
+    int32_t verdict = 0;
+    HIPCHK(hipMemcpyAsync(&d, a.stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&verdict, a.verdicts, 4, hipMemcpyDeviceToHost, s));
+    if (model && p->hp.A > 0)
+        HIPCHK(hipMemcpyAsync(model, a.models, (size_t)p->hp.A, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats) to_stats(d, stats);
+    return verdict;
+}
+
+int32_t asp_state_export(asp_program* p, void* stream, asp_state* st) {
+    if (!p || !p->bound || !st) return fail(ASP_E_STATE, "program not bound or null state");
+    hipStream_t s = (hipStream_t)stream;
+    SlotCtrl k;
+    int32_t rc = read_ctrl(p, s, &k);
+    if (rc) return rc;
+    const int32_t V = p->hp.V, W = p->opt.W;
+    st->n_vars = V;
+    st->W = W;
+    st->cdl = k.cdl;
+    st->frontier_len = k.qt - k.qh;
+    st->n_learned = k.n_learned;
+    st->pending = k.pend_kind == 1 ? k.pending : -1;
+    st->learned_lits = k.learned_lits;
+    st->initialised = k.init_done;
+    st->status = k.status;
+    ctrl_stats(k, &st->stats);
+    if (!st->val) return ASP_OK;
+    const SlotLayout& L = p->plan.lay;
+    auto get = [&](void* dst, int64_t off, size_t bytes) -> hipError_t {
+        if (!dst || bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(dst, p->arena + p->plan.off_slots + off, bytes,
+                              hipMemcpyDeviceToHost, s);
+    };
+    HIPCHK(get(st->val, L.val8, (size_t)V + 1));
+    HIPCHK(get(st->lvl, L.lvl, 4 * ((size_t)V + 1)));
+    HIPCHK(get(st->deps, L.deps, 8 * ((size_t)V + 1) * W));
+    HIPCHK(get(st->dec, L.dec, 4 * ((size_t)k.cdl + 1)));
+    HIPCHK(get(st->frontier, L.trail + 4 * (int64_t)k.qh, 4 * (size_t)(k.qt - k.qh)));
+    HIPCHK(get(st->learned_off, L.l_off, 4 * ((size_t)k.n_learned + 1)));
+    HIPCHK(get(st->learned, L.l_lits, 4 * (size_t)k.learned_lits));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st->dec) {
+        st->dec[0] = 0;
+        if (k.cdl >= 1) st->dec[1] = 0;
+    }
+    if (st->frontier) std::sort(st->frontier, st->frontier + (k.qt - k.qh));
+    return ASP_OK;
+}
+
+int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
+    if (!p || !p->bound || !st) return fail(ASP_E_STATE, "program not bound or null state");
+    const int32_t V = p->hp.V, W = p->opt.W, A = p->hp.A, Rh = p->hp.Rh;
+    const int32_t nS = (int32_t)p->hp.n_nogoods();
+    if (st->n_vars != V || st->W != W) return fail(ASP_E_INVALID, "state shape mismatch");
+    if (!st->val || !st->lvl || !st->deps || !st->dec) return fail(ASP_E_INVALID, "null state arrays");
+    const int32_t cdl = st->cdl;
+    if (cdl < 1 || cdl > Rh + 1) return fail(ASP_E_INVALID, "cdl out of range");
+    if (st->n_learned < 0 || st->n_learned > p->opt.learned_cap_ng ||
+        st->learned_lits < 0 || st->learned_lits > p->opt.learned_cap_lits)
+        return fail(ASP_E_CAPACITY, "learned store beyond capacity");
+    if (st->n_learned > 0 && (!st->learned_off || !st->learned))
+        return fail(ASP_E_INVALID, "null learned arrays");
+    std::vector<uint8_t> infront(V + 1, 0);
+    for (int32_t i = 0; i < st->frontier_len; ++i) {
+        int32_t v = st->frontier[i];
+        if (v < 1 || v > V || st->val[v] == 0 || st->lvl[v] != cdl)
+            return fail(ASP_E_INVALID, "frontier variable not assigned at level cdl");
+        infront[v] = 1;
+    }
+    std::vector<int32_t> trail;
+    for (int32_t v = 1; v <= V; ++v) {
+        int8_t x = st->val[v];
+        if (x < -1 || x > 1) return fail(ASP_E_INVALID, "value out of range");
+        if (x == 0 && st->lvl[v] != 0) return fail(ASP_E_INVALID, "level of unassigned variable");
+        if (x != 0 && (st->lvl[v] < 1 || st->lvl[v] > cdl)) return fail(ASP_E_INVALID, "level out of range");
+        if (x != 0) trail.push_back(v);
+    }
+    std::stable_sort(trail.begin(), trail.end(), [&](int32_t a, int32_t b) {
+        if (st->lvl[a] != st->lvl[b]) return st->lvl[a] < st->lvl[b];
+        return infront[a] < infront[b];
+    });
+    std::vector<int32_t> tlim(Rh + 3, 0);
+    {
+        size_t k = 0;
+        for (int32_t l = 1; l <= cdl + 1 && l < Rh + 3; ++l) {
+            while (k < trail.size() && st->lvl[trail[k]] < l) ++k;
+            tlim[l] = (int32_t)k;
+        }
+    }
+    for (int32_t l = 2; l <= cdl; ++l) {
+        int32_t d = st->dec[l];
+        if (d <= A || d > V || (d - A - 1) % 3 != 0 || st->val[d] != 1 || st->lvl[d] != l)
+            return fail(ASP_E_INVALID, "decision literal of a level is not an assigned b variable");
+    }
+    // learned nogoods and their occurrence lists (exact-size arrays)
+    const int32_t nL = st->n_learned;
+    std::vector<int32_t> loff(nL + 1, 0), llits(st->learned_lits);
+    for (int32_t j = 0; j <= nL; ++j) loff[j] = nL ? st->learned_off[j] : 0;
+    if (loff[0] != 0 || loff[nL] != st->learned_lits) return fail(ASP_E_INVALID, "learned offsets");
+    for (int64_t q = 0; q < st->learned_lits; ++q) {
+        int32_t l = st->learned[q];
+        if (l == 0 || l > V || l < -V) return fail(ASP_E_INVALID, "learned literal out of range");
+        llits[q] = l;
+    }
+    const size_t NL = 2 * ((size_t)V + 1);
+    std::vector<int32_t> lptr(NL, 0), ln(NL, 0), lcap(NL, 0), pool;
+    for (int32_t j = 0; j < nL; ++j)
+        for (int32_t q = loff[j]; q < loff[j + 1]; ++q) {
+            int32_t l = llits[q];
+            ln[2 * (l < 0 ? -l : l) + (l < 0)] += 1;
+        }
+    {
+        int32_t run = 0;
+        for (size_t i = 0; i < NL; ++i) {
+            lptr[i] = run;
+            lcap[i] = ln[i];
+            run += ln[i];
+        }
+        pool.assign(run, 0);
+        std::vector<int32_t> fill(lptr);
+        for (int32_t j = 0; j < nL; ++j)
+            for (int32_t q = loff[j]; q < loff[j + 1]; ++q) {
+                int32_t l = llits[q];
+                pool[fill[2 * (l < 0 ? -l : l) + (l < 0)]++] = nS + j;
+            }
+        if ((int64_t)pool.size() > p->plan.lay.pool_cap) return fail(ASP_E_CAPACITY, "pool");
+    }
+    SlotCtrl k;
+    memset(&k, 0, sizeof(k));
+    k.inst = 0;
+    k.cdl = cdl;
+    k.qt = (int32_t)trail.size();
+    k.qh = k.qt - st->frontier_len;
+    k.n_learned = nL;
+    k.pool_top = (int32_t)pool.size();
+    k.pending = st->pending;
+    k.pend_kind = st->pending >= 0 ? 1 : 0;
+    if (st->pending >= nS + nL) return fail(ASP_E_INVALID, "pending conflict id");
+    k.status = ASP_RUNNING;
+    k.init_done = st->initialised ? 1 : 0;
+    k.last_step = st->stats.last_step;
+    k.learned_lits = st->learned_lits;
+    k.rounds = st->stats.rounds;
+    k.visits = st->stats.visits;
+    k.checks = st->stats.literal_checks;
+    k.props = st->stats.propagations;
+    k.decisions = st->stats.decisions;
+    k.conflicts = st->stats.conflicts;
+    k.learned = st->stats.learned;
+    k.learned_len = st->stats.learned_len;
+    k.gate_fail = st->stats.gate_failures;
+    k.completes = st->stats.completes;
+    k.hash = st->stats.trace_hash;
+    std::vector<int32_t> dec(Rh + 3, 0);
+    for (int32_t l = 2; l <= cdl; ++l) dec[l] = st->dec[l];
+    std::vector<int32_t> win(V + 1, 0x7fffffff);
+    std::vector<int32_t> lvl(st->lvl, st->lvl + V + 1);
+    hipStream_t s = (hipStream_t)stream;
+    const SlotLayout& L = p->plan.lay;
+    auto put = [&](int64_t off, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(p->arena + p->plan.off_slots + off, src, bytes,
+                              hipMemcpyHostToDevice, s);
+    };
+    HIPCHK(put(L.ctrl, &k, sizeof(k)));
+    HIPCHK(put(L.val8, st->val, (size_t)V + 1));
+    HIPCHK(put(L.lvl, lvl.data(), 4 * lvl.size()));
+    HIPCHK(put(L.deps, st->deps, 8 * ((size_t)V + 1) * W));
+    HIPCHK(put(L.win, win.data(), 4 * win.size()));
+    HIPCHK(put(L.trail, trail.data(), 4 * trail.size()));
+    HIPCHK(put(L.tlim, tlim.data(), 4 * tlim.size()));
+    HIPCHK(put(L.dec, dec.data(), 4 * dec.size()));
+    HIPCHK(put(L.locc_ptr, lptr.data(), 4 * lptr.size()));
+    HIPCHK(put(L.locc_n, ln.data(), 4 * ln.size()));
+    HIPCHK(put(L.locc_cap, lcap.data(), 4 * lcap.size()));
+    HIPCHK(put(L.l_off, loff.data(), 4 * loff.size()));
+    HIPCHK(put(L.l_lits, llits.data(), 4 * llits.size()));
+    HIPCHK(put(L.pool, pool.data(), 4 * pool.size()));
+    HIPCHK(hipStreamSynchronize(s));
+    return ASP_OK;
+}
+
+// ---------------------------------------------------------------- batches
+int32_t asp_batch_create(int32_t n, asp_program* const* progs, const asp_schedule* sched,
+                         asp_batch** out, uint64_t* device_bytes, uint64_t* model_bytes) {
+    if (!out || n < 1 || !progs) return fail(ASP_E_INVALID, "empty batch or null output");
+    *out = nullptr;
+    int32_t threads = sched ? sched->threads : 64;
+    int32_t wpc = sched ? sched->wg_per_cu : 8;
+    if (!valid_threads(threads) || wpc < 1) return fail(ASP_E_INVALID, "bad schedule");
+    std::unique_ptr<asp_batch> b(new asp_batch());
+    b->opt = progs[0] ? progs[0]->opt : default_options();
+    for (int32_t i = 0; i < n; ++i) {
+        if (!progs[i]) return fail(ASP_E_INVALID, "null program in batch");
+        const asp_options& o = progs[i]->opt;
+        if (o.W != b->opt.W || o.gate != b->opt.gate || o.learned_cap_ng != b->opt.learned_cap_ng ||
+            o.learned_cap_lits != b->opt.learned_cap_lits)
+            return fail(ASP_E_INVALID, "batch programs must share their options");
+        b->progs.push_back(&progs[i]->hp);
+    }
+    DeviceInfo di = device_info();
+    if (!di.ok) return fail(ASP_E_DEVICE, "no HIP device");
+    Plan probe;
+    int32_t rc = make_plan(b->progs, b->opt, threads, 1, probe);
+    if (rc) return rc;
+    int occ = 0;
+    if (occupancy(threads, probe.lds, &occ) != hipSuccess || occ < 1) occ = 1;
+    int32_t grid = di.cus * std::min(wpc, occ);
+    rc = make_plan(b->progs, b->opt, threads, grid, b->plan);
+    if (rc) return rc;
+    if (device_bytes) *device_bytes = b->plan.total;
+    if (model_bytes) *model_bytes = (uint64_t)b->plan.tot_model;
+    *out = b.release();
+    return ASP_OK;
+}
+
+int32_t asp_batch_bind(asp_batch* b, void* dev_arena, uint64_t bytes, void* stream) {
+    if (!b || !dev_arena) return fail(ASP_E_INVALID, "null batch or arena");
+    if ((uintptr_t)dev_arena % kAlign) return fail(ASP_E_INVALID, "arena must be 256-byte aligned");
+    if (bytes < b->plan.total) return fail(ASP_E_CAPACITY, "arena too small");
+    b->arena = (uint8_t*)dev_arena;
+    int32_t rc = upload_static(b->progs, b->plan, b->arena, (hipStream_t)stream);
+    if (rc) return rc;
+    b->bound = true;
+    return ASP_OK;
+}
+
+int32_t asp_solve_batch(asp_batch* b, void* stream, const asp_limits* lim) {
+    if (!b || !b->bound) return fail(ASP_E_STATE, "batch not bound");
+    hipStream_t s = (hipStream_t)stream;
+    DeviceInfo di = device_info();
+    int32_t rc = check_launch(b->plan, di);
+    if (rc) return rc;
+    KArgs a = make_args(b->plan, b->arena, MODE_SOLVE);
+    apply_limits(a, b->plan, lim, di);
+    if (!b->ev0) {
+        HIPCHK(hipEventCreate(&b->ev0));
+        HIPCHK(hipEventCreate(&b->ev1));
+    }
+    HIPCHK(launch_reset_queue(a.queue, s));
+    HIPCHK(hipEventRecord(b->ev0, s));
+    HIPCHK(launch_search(a, b->plan.threads, b->plan.grid, b->plan.lds, s));
+    HIPCHK(hipEventRecord(b->ev1, s));
+    b->timed = true;
+    return ASP_OK;
+}
+
+int32_t asp_batch_results(asp_batch* b, void* stream, int32_t* verdicts, uint8_t* models,
+                          asp_stats* stats) {
+    if (!b || !b->bound) return fail(ASP_E_STATE, "batch not bound");
+    hipStream_t s = (hipStream_t)stream;
+    const Plan& P = b->plan;
+    if (verdicts)
+        HIPCHK(hipMemcpyAsync(verdicts, b->arena + P.off_verd, 4 * (size_t)P.n,
+                              hipMemcpyDeviceToHost, s));
+    if (models && P.tot_model > 0)
+        HIPCHK(hipMemcpyAsync(models, b->arena + P.off_models, (size_t)P.tot_model,
+                              hipMemcpyDeviceToHost, s));
+    std::vector<DevStats> ds;
+    if (stats) {
+        ds.resize(P.n);
+        HIPCHK(hipMemcpyAsync(ds.data(), b->arena + P.off_stats, sizeof(DevStats) * ds.size(),
+                              hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats)
+        for (int32_t i = 0; i < P.n; ++i) to_stats(ds[i], &stats[i]);
+    return ASP_OK;
+}
+
+int32_t asp_batch_last_ms(asp_batch* b, double* ms) {
+    if (!b || !b->timed || !ms) return fail(ASP_E_STATE, "no timed launch");
+    HIPCHK(hipEventSynchronize(b->ev1));
+    float f = 0.f;
+    HIPCHK(hipEventElapsedTime(&f, b->ev0, b->ev1));
+    *ms = (double)f;
+    return ASP_OK;
+}
+
+int32_t asp_batch_free(asp_batch* b) {
+    if (b) {
+        if (b->ev0) (void)hipEventDestroy(b->ev0);
+        if (b->ev1) (void)hipEventDestroy(b->ev1);
+        delete b;
+    }
+    return ASP_OK;
+}
+
+}  // extern "C"

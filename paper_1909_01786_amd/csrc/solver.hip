@@ -1,0 +1,1100 @@
+// solver.hip -- device search of libasp for gfx950 (CDNA4, wave64).
+//
+// One workgroup runs one instance's whole conflict-driven search (Alg. 1 of
+// the paper): InitialPropagation, PropagateAndCheck rounds (Sect. 4.1),
+// Fwd-learning from Deps bitmaps with Backjump (Sect. 4.2), the
+// ASP-computation Decision and CompleteAssignment (Sect. 2), and a stability
+// check of total assignments.  In the batched form the workgroups are
+// persistent and take instances, largest first, from a queue.
+//
+// Data placement:
+//  * LDS: the assignment as 2 bits per variable (1 = true, 2 = false) and a
+//    second 2-bit map of the values implied in the current round; scan
+//    buffers that spread a round's (literal, nogood) visits over the lanes.
+//  * HBM (read-only, per instance): nogood CSR, literal->nogood map CSR,
+//    rule table.  Visits read a map segment and then the nogood's literals.
+//  * HBM (per workgroup slot): levels, Deps bitmaps (W x 64 bit per
+//    variable), the trail (assigned variables in order, whose tail is the
+//    round frontier), the lowest-id implier per variable, the learned
+//    nogoods and their literal occurrence lists.
+//
+// Control discipline: the search state (levels, queue pointers, counters,
+// status) is a struct that every lane of every wave holds and updates
+// identically; it is derived only from values that all lanes see alike (LDS
+// words read after a barrier, uniform global loads, block reductions), and
+// is pinned to scalar registers with readfirstlane.  No branch of the
+// control flow depends on the lane index, so the compiler cannot give lanes
+// different paths through the search loop, and single-writer effects are
+// value selects or identical stores from every lane.
+//
+// A round is a Jacobi step: every nogood reached from the previous round's
+// assignments is classified against the same assignment; among the nogoods
+// implying a variable the lowest id wins (its Deps come from it), and a
+// unit nogood implying the other value is a conflict.  The conflict kept is
+// the shortest (then lowest id) violated or losing nogood.  This makes the
+// search deterministic, where the paper's atomicSet picks any thread.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.h"
+
+namespace asp {
+
+#define DEV __device__ __forceinline__
+
+constexpr uint32_t VT = 1u, VF = 2u;          // 2-bit value codes
+constexpr int32_t WIN_NONE = 0x7fffffff;
+constexpr uint64_t FNV_BASIS = 1469598103934665603ull;
+constexpr uint64_t FNV_PRIME = 1099511628211ull;
+constexpr int kMaxWaves = 16;
+
+// Uniform search state: identical in every lane.
+struct Ctl {
+    int32_t inst, A, Rh, V, nS, u0, u1, has_empty;
+    int32_t cdl, qh, qt, n_learned, pend_kind, pending, status, init_done, last_step, pool_top;
+    int64_t learned_lits, rounds, props, decisions, conflicts, learned, learned_len, gate_fail,
+            completes, steps, visits, checks;
+    uint64_t hash;
+};
+
+// LDS words through which lanes exchange per-phase results.
+struct Scr {
+    unsigned long long conf_key;
+    int32_t tail, clash, changed, pool_top, cap_err;
+    int32_t popq[kMaxWaves];
+    int32_t flag[kMaxWaves];
+    int32_t wsum[kMaxWaves + 1];
+    unsigned long long red[kMaxWaves];
+};
+
+struct Ctx {
+    // per-instance static arrays
+    const int32_t *NO, *NL, *MO, *MI, *RH, *RO, *RBO, *RBL;
+    // per-slot arrays
+    SlotCtrl* ctrl;
+    int8_t* val8;
+    int32_t *lvl, *win, *trail, *tlim, *dec, *lptr, *ln, *lcap, *loff, *llits, *pool;
+    uint64_t* deps;
+    int64_t pool_cap;
+    // LDS
+    uint32_t *valb, *pendb;
+    int32_t *sOff, *sS0, *sCs, *sL0;
+    unsigned long long* sB;
+    Scr* scr;
+    int32_t W, T, tid, lane, wid, nw;
+    unsigned long long my_visits, my_checks;
+};
+
+// ------------------------------------------------------------ helpers
+DEV void bar() { __syncthreads(); }
+DEV int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+DEV int64_t uni64(int64_t x) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+DEV uint32_t vget(const uint32_t* b, int v) { return (b[v >> 4] >> ((v & 15) << 1)) & 3u; }
+DEV void vset(uint32_t* b, int v, uint32_t code) { atomicOr(&b[v >> 4], code << ((v & 15) << 1)); }
+DEV void vclr(uint32_t* b, int v) { atomicAnd(&b[v >> 4], ~(3u << ((v & 15) << 1))); }
+DEV uint32_t lcode(int l) { return l > 0 ? VT : VF; }     // value making literal l true
+DEV int lvar(int l) { return l < 0 ? -l : l; }
+DEV int lidx(int l) { return 2 * lvar(l) + (l < 0 ? 1 : 0); }
+
+DEV int32_t ld_agent(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV void st_agent(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+DEV uint64_t fnv(uint64_t h, int32_t w) {
+    uint32_t u = (uint32_t)w;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        h ^= (uint64_t)((u >> (8 * q)) & 0xffu);
+        h *= FNV_PRIME;
+    }
+    return h;
+}
+
+DEV int wave_incl_scan(int x, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan over the block; every lane must call it.
+DEV int block_excl_scan(Ctx& c, int x, int* total) {
+    const int inc = wave_incl_scan(x, c.lane);
+    const int wtot = __shfl(inc, 63, 64);
+    bar();
+    c.scr->wsum[c.wid] = wtot;   // every lane of the wave stores the same value
+    bar();
+    int before = 0, all = 0;
+    for (int i = 0; i < c.nw; ++i) {
+        int s = c.scr->wsum[i];
+        before += i < c.wid ? s : 0;
+        all += s;
+    }
+    *total = uni(all);
+    return inc - x + before;
+}
+
+DEV unsigned long long block_max_u64(Ctx& c, unsigned long long x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        unsigned long long y = __shfl_xor(x, d, 64);
+        x = x > y ? x : y;
+    }
+    bar();
+    c.scr->red[c.wid] = x;
+    bar();
+    unsigned long long r = 0;
+    for (int i = 0; i < c.nw; ++i) r = r > c.scr->red[i] ? r : c.scr->red[i];
+    return (unsigned long long)uni64((int64_t)r);
+}
+
+DEV unsigned long long block_sum_u64(Ctx& c, unsigned long long x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    bar();
+    c.scr->red[c.wid] = x;
+    bar();
+    unsigned long long r = 0;
+    for (int i = 0; i < c.nw; ++i) r += c.scr->red[i];
+    return (unsigned long long)uni64((int64_t)r);
+}
+
+DEV int block_min_i32(Ctx& c, int x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        int y = __shfl_xor(x, d, 64);
+        x = x < y ? x : y;
+    }
+    bar();
+    c.scr->red[c.wid] = (unsigned long long)(uint32_t)x;
+    bar();
+    int r = 0x7fffffff;
+    for (int i = 0; i < c.nw; ++i) {
+        int v = (int)(uint32_t)c.scr->red[i];
+        r = r < v ? r : v;
+    }
+    return uni(r);
+}
+
+// OR of a per-wave flag over the block.
+DEV int block_any(Ctx& c, int f) {
+    bar();
+    c.scr->flag[c.wid] = f;
+    bar();
+    int r = 0;
+    for (int i = 0; i < c.nw; ++i) r |= c.scr->flag[i];
+    return uni(r);
+}
+
+DEV void ng_span(const Ctx& c, const Ctl& k, int id, const int32_t*& p, int& len) {
+    if (id < k.nS) {
+        int b = c.NO[id];
+        p = c.NL + b;
+        len = c.NO[id + 1] - b;
+    } else {
+        int j = id - k.nS;
+        int b = c.loff[j];
+        p = c.llits + b;
+        len = c.loff[j + 1] - b;
+    }
+}
+
+// Deps bit of the decision at level l >= 2; the last bit stands for every
+// level >= 64W.
+DEV int level_bit(int l, int W) {
+    int b = l - 1, top = 64 * W - 1;
+    return b < top ? b : top;
+}
+
+// Bits of every decision level 2..cdl, word w.
+DEV unsigned long long alldec_word(int w, int cdl, int W) {
+    int hi = cdl - 1;
+    int top = 64 * W - 1;
+    if (hi > top) hi = top;
+    if (hi < 1) return 0ull;
+    int lo = 1;
+    int b0 = 64 * w, b1 = 64 * w + 63;
+    int a = lo > b0 ? lo : b0, z = hi < b1 ? hi : b1;
+    if (a > z) return 0ull;
+    int n = z - a + 1;
+    unsigned long long m = n == 64 ? ~0ull : ((1ull << n) - 1ull);
+    return m << (a - b0);
+}
+
+// --------------------------------------------------------- state moves
+DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst, uint8_t* slot) {
+    const InstDesc& d = a.inst[inst];
+    c.NO = a.ng_off + d.ng_off;
+    c.NL = a.ng_lits + d.ng_lits;
+    c.MO = a.map_off + d.map_off;
+    c.MI = a.map_ids + d.map_ids;
+    c.RH = a.rule_head + d.rules;
+    c.RO = a.rule_occ + d.rules;
+    c.RBO = a.rb_off + d.rb_off;
+    c.RBL = a.rb_lits + d.rb_lits;
+    c.ctrl = (SlotCtrl*)(slot + a.lay.ctrl);
+    c.val8 = (int8_t*)(slot + a.lay.val8);
+    c.lvl = (int32_t*)(slot + a.lay.lvl);
+    c.deps = (uint64_t*)(slot + a.lay.deps);
+    c.win = (int32_t*)(slot + a.lay.win);
+    c.trail = (int32_t*)(slot + a.lay.trail);
+    c.tlim = (int32_t*)(slot + a.lay.tlim);
+    c.dec = (int32_t*)(slot + a.lay.dec);
+    c.lptr = (int32_t*)(slot + a.lay.locc_ptr);
+    c.ln = (int32_t*)(slot + a.lay.locc_n);
+    c.lcap = (int32_t*)(slot + a.lay.locc_cap);
+    c.loff = (int32_t*)(slot + a.lay.l_off);
+    c.llits = (int32_t*)(slot + a.lay.l_lits);
+    c.pool = (int32_t*)(slot + a.lay.pool);
+    c.pool_cap = a.lay.pool_cap;
+    k.inst = inst;
+    k.A = uni(d.A);
+    k.Rh = uni(d.Rh);
+    k.V = uni(d.V);
+    k.nS = uni(d.n_static);
+    k.u0 = uni(d.u0);
+    k.u1 = uni(d.u1);
+    k.has_empty = uni(d.has_empty);
+}
+
+// Fresh search state: nothing assigned, no learned nogoods.
+DEV void reset_search(Ctx& c, Ctl& k) {
+    const int V = k.V, W = c.W, T = c.T, tid = c.tid;
+    const int words = (V + 1 + 15) >> 4;
+    for (int i = tid; i < words; i += T) {
+        c.valb[i] = 0u;
+        c.pendb[i] = 0u;
+    }
+    for (int v = tid; v <= V; v += T) {
+        c.lvl[v] = 0;
+        c.val8[v] = 0;
+        st_agent(&c.win[v], WIN_NONE);
+    }
+    for (int q = tid; q < (V + 1) * W; q += T) c.deps[q] = 0ull;
+    for (int q = tid; q < 2 * (V + 1); q += T) {
+        c.ln[q] = 0;
+        c.lcap[q] = 0;
+        c.lptr[q] = 0;
+    }
+    for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
+    c.loff[0] = 0;
+    k.cdl = 1;
+    k.qh = k.qt = 0;
+    k.n_learned = 0;
+    k.pool_top = 0;
+    k.pending = -1;
+    k.pend_kind = 0;
+    k.status = ST_RUNNING;
+    k.init_done = 0;
+    k.last_step = STEP_NONE;
+    k.learned_lits = 0;
+    k.rounds = k.props = k.decisions = k.conflicts = 0;
+    k.learned = k.learned_len = k.gate_fail = k.completes = 0;
+    k.visits = k.checks = 0;
+    k.hash = FNV_BASIS;
+    k.steps = 0;
+    __threadfence();
+    bar();
+}
+
+DEV void load_ctrl(Ctx& c, Ctl& k) {
+    const int V = k.V, T = c.T, tid = c.tid;
+    const int words = (V + 1 + 15) >> 4;
+    for (int i = tid; i < words; i += T) c.pendb[i] = 0u;
+    for (int i = tid; i < words; i += T) {
+        uint32_t wv = 0;
+        for (int q = 0; q < 16; ++q) {
+            int v = i * 16 + q;
+            if (v > V) break;
+            int8_t x = c.val8[v];
+            uint32_t code = x > 0 ? VT : (x < 0 ? VF : 0u);
+            wv |= code << (2 * q);
+        }
+        c.valb[i] = wv;
+    }
+    for (int w = tid; w < c.W; w += T) c.sB[w] = c.ctrl->pend_B[w];
+    const SlotCtrl& g = *c.ctrl;
+    k.cdl = uni(g.cdl);
+    k.qh = uni(g.qh);
+    k.qt = uni(g.qt);
+    k.n_learned = uni(g.n_learned);
+    k.pool_top = uni(g.pool_top);
+    k.pending = uni(g.pending);
+    k.pend_kind = uni(g.pend_kind);
+    k.status = uni(g.status);
+    k.init_done = uni(g.init_done);
+    k.last_step = uni(g.last_step);
+    k.learned_lits = uni64(g.learned_lits);
+    k.rounds = uni64(g.rounds);
+    k.visits = uni64(g.visits);
+    k.checks = uni64(g.checks);
+    k.props = uni64(g.props);
+    k.decisions = uni64(g.decisions);
+    k.conflicts = uni64(g.conflicts);
+    k.learned = uni64(g.learned);
+    k.learned_len = uni64(g.learned_len);
+    k.gate_fail = uni64(g.gate_fail);
+    k.completes = uni64(g.completes);
+    k.hash = (uint64_t)uni64((int64_t)g.hash);
+    k.steps = 0;
+    bar();
+}
+
+// Fold every lane's visit and check counts into the uniform state.
+DEV void flush_counters(Ctx& c, Ctl& k) {
+    k.visits += (int64_t)block_sum_u64(c, c.my_visits);
+    k.checks += (int64_t)block_sum_u64(c, c.my_checks);
+    c.my_visits = c.my_checks = 0ull;
+    bar();
+}
+
+// Every lane stores the same control values (identical stores).
+DEV void save_ctrl(Ctx& c, const Ctl& k) {
+    const int V = k.V, T = c.T, tid = c.tid;
+    for (int v = tid; v <= V; v += T) {
+        uint32_t code = vget(c.valb, v);
+        c.val8[v] = code == VT ? (int8_t)1 : (code == VF ? (int8_t)-1 : (int8_t)0);
+    }
+    for (int w = tid; w < c.W; w += T) c.ctrl->pend_B[w] = c.sB[w];
+    SlotCtrl& g = *c.ctrl;
+    g.inst = k.inst;
+    g.cdl = k.cdl;
+    g.qh = k.qh;
+    g.qt = k.qt;
+    g.n_learned = k.n_learned;
+    g.pool_top = k.pool_top;
+    g.pending = k.pending;
+    g.pend_kind = k.pend_kind;
+    g.status = k.status;
+    g.init_done = k.init_done;
+    g.last_step = k.last_step;
+    g.learned_lits = k.learned_lits;
+    g.rounds = k.rounds;
+    g.visits = k.visits;
+    g.checks = k.checks;
+    g.props = k.props;
+    g.decisions = k.decisions;
+    g.conflicts = k.conflicts;
+    g.learned = k.learned;
+    g.learned_len = k.learned_len;
+    g.gate_fail = k.gate_fail;
+    g.completes = k.completes;
+    g.hash = k.hash;
+    __threadfence();
+    bar();
+}
+
+// ------------------------------------------------------------- steps
+// InitialPropagation (Alg. 1): each unit nogood {l} assigns the complement
+// of l at level 1 with empty Deps; opposite units mean no answer set.
+DEV void step_init(Ctx& c, Ctl& k) {
+    const int T = c.T, tid = c.tid;
+    c.scr->clash = k.has_empty;
+    c.scr->tail = k.qt;
+    bar();
+    if (!k.has_empty) {
+        for (int id = k.u0 + tid; id < k.u1; id += T) {
+            int l = c.NL[c.NO[id]];
+            int x = lvar(l);
+            uint32_t code = l > 0 ? VF : VT;
+            uint32_t sh = (uint32_t)(x & 15) << 1;
+            uint32_t old = atomicOr(&c.pendb[x >> 4], code << sh);
+            uint32_t ob = (old >> sh) & 3u;
+            if (ob == 0u) {
+                int pos = atomicAdd(&c.scr->tail, 1);
+                c.trail[pos] = x;
+            } else if ((ob | code) == 3u) {
+                c.scr->clash = 1;
+            }
+        }
+    }
+    __threadfence();
+    bar();
+    const int q0 = k.qt;
+    const int q1 = uni(c.scr->tail);
+    const int clash = uni(c.scr->clash);
+    if (!clash) {
+        for (int i = q0 + tid; i < q1; i += T) {
+            int x = c.trail[i];
+            uint32_t code = vget(c.pendb, x);
+            vset(c.valb, x, code);
+            c.lvl[x] = 1;
+        }
+    }
+    bar();
+    for (int i = q0 + tid; i < q1; i += T) vclr(c.pendb, c.trail[i]);
+    __threadfence();
+    bar();
+    k.init_done = 1;
+    if (clash) {
+        k.status = ST_UNSAT;
+    } else {
+        k.qh = q0;
+        k.qt = q1;
+    }
+}
+
+// Classification of one visited nogood against the round's snapshot.
+// pass 0: record violations and unit implications; pass 1: conflicts of
+// unit nogoods that lost their variable to a lower-id implier of the
+// other value.
+DEV void visit_one(Ctx& c, const Ctl& k, int id, int pass) {
+    const int32_t* lits;
+    int len;
+    ng_span(c, k, id, lits, len);
+    if (pass == 0) {
+        c.my_visits += 1ull;
+        c.my_checks += (unsigned long long)len;
+    }
+    int open = 0, u = 0;
+    for (int q = 0; q < len; ++q) {
+        int l = lits[q];
+        uint32_t s = vget(c.valb, lvar(l));
+        if (s == 0u) {
+            if (++open > 1) return;
+            u = l;
+        } else if (s != lcode(l)) {
+            return;  // satisfied
+        }
+    }
+    if (open == 0) {
+        if (pass == 0)
+            atomicMin(&c.scr->conf_key, ((unsigned long long)(uint32_t)len << 32) | (uint32_t)id);
+        return;
+    }
+    const int x = lvar(u);
+    const uint32_t code = u > 0 ? VF : VT;   // implied value of x
+    if (pass == 0) {
+        atomicMin(&c.win[x], id * 2 + (code == VF ? 1 : 0));
+        uint32_t sh = (uint32_t)(x & 15) << 1;
+        uint32_t old = atomicOr(&c.pendb[x >> 4], code << sh);
+        uint32_t ob = (old >> sh) & 3u;
+        if (ob == 0u) {
+            int pos = atomicAdd(&c.scr->tail, 1);
+            c.trail[pos] = x;
+        } else if ((ob | code) == 3u) {
+            c.scr->clash = 1;
+        }
+    } else {
+        int key = ld_agent(&c.win[x]);
+        uint32_t wcode = (key & 1) ? VF : VT;
+        if (wcode != code)
+            atomicMin(&c.scr->conf_key, ((unsigned long long)(uint32_t)len << 32) | (uint32_t)id);
+    }
+}
+
+// Spread the visits of frontier trail[qh..qt) over the block: each frontier
+// variable contributes its static map segment and its learned occurrence
+// list; an exclusive scan of the segment sizes gives each lane its visits.
+DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
+    const int T = c.T, tid = c.tid;
+    for (int base = qh; base < qt; base += T) {
+        const int f = base + tid;
+        int s0 = 0, cs = 0, l0 = 0, cl = 0;
+        if (f < qt) {
+            int v = c.trail[f];
+            int L = vget(c.valb, v) == VT ? v : -v;
+            int li = lidx(L);
+            s0 = c.MO[li];
+            cs = c.MO[li + 1] - s0;
+            l0 = c.lptr[li];
+            cl = c.ln[li];
+        }
+        int total;
+        int off = block_excl_scan(c, cs + cl, &total);
+        c.sOff[tid] = off;
+        c.sS0[tid] = s0;
+        c.sCs[tid] = cs;
+        c.sL0[tid] = l0;
+        bar();
+        const int nf = (qt - base) < T ? (qt - base) : T;
+        for (int q = tid; q < total; q += T) {
+            int lo = 0, hi = nf - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (c.sOff[mid] <= q) lo = mid; else hi = mid - 1;
+            }
+            int j = q - c.sOff[lo];
+            int cnt = c.sCs[lo];
+            int id = j < cnt ? c.MI[c.sS0[lo] + j] : c.pool[c.sL0[lo] + (j - cnt)];
+            visit_one(c, k, id, pass);
+        }
+        bar();
+    }
+}
+
+// One PropagateAndCheck round (Sect. 4.1, Alg. 2) in Jacobi form.
+DEV void step_round(Ctx& c, Ctl& k) {
+    const int T = c.T, tid = c.tid, W = c.W;
+    const int qh = k.qh, qt = k.qt, cdl = k.cdl;
+    c.scr->conf_key = ~0ull;
+    c.scr->clash = 0;
+    c.scr->tail = qt;
+    bar();
+    visit_pass(c, k, qh, qt, 0);
+    __threadfence();
+    bar();
+    if (uni(c.scr->clash)) {
+        visit_pass(c, k, qh, qt, 1);
+        __threadfence();
+        bar();
+    }
+    const int nt = uni(c.scr->tail);
+    // apply every implication, its Deps being the OR of the Deps of the
+    // other variables of the winning nogood (mk_dl_bitmap)
+    for (int i = qt + tid; i < nt; i += T) {
+        int x = c.trail[i];
+        int key = ld_agent(&c.win[x]);
+        int id = key >> 1;
+        uint32_t code = (key & 1) ? VF : VT;
+        const int32_t* lits;
+        int len;
+        ng_span(c, k, id, lits, len);
+        uint64_t* dx = c.deps + (size_t)x * W;
+        if (W == 1) {
+            unsigned long long acc = 0ull;
+            for (int q = 0; q < len; ++q) {
+                int y = lvar(lits[q]);
+                if (y != x) acc |= c.deps[y];
+            }
+            dx[0] = acc;
+        } else {
+            for (int w = 0; w < W; ++w) dx[w] = 0ull;
+            for (int q = 0; q < len; ++q) {
+                int y = lvar(lits[q]);
+                if (y == x) continue;
+                const uint64_t* dy = c.deps + (size_t)y * W;
+                for (int w = 0; w < W; ++w) dx[w] |= dy[w];
+            }
+        }
+        c.lvl[x] = cdl;
+        vset(c.valb, x, code);
+        vclr(c.pendb, x);
+        st_agent(&c.win[x], WIN_NONE);
+    }
+    __threadfence();
+    bar();
+    const unsigned long long ck = (unsigned long long)uni64((int64_t)c.scr->conf_key);
+    bar();
+    k.qh = qt;
+    k.qt = nt;
+    k.rounds += 1;
+    k.props += nt - qt;
+    if (ck != ~0ull) {
+        k.pending = (int32_t)(uint32_t)(ck & 0xffffffffull);
+        k.pend_kind = 1;
+    }
+}
+
+// Fwd-learning (Sect. 4.2, Alg. 4) + Backjump + assertion.
+DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
+    const int T = c.T, tid = c.tid, W = c.W;
+    c.scr->pool_top = k.pool_top;
+    c.scr->cap_err = 0;
+    if (k.pend_kind == 1) {
+        // B = OR of the Deps of every variable of the conflict nogood
+        for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
+        bar();
+        const int32_t* lits;
+        int len;
+        ng_span(c, k, k.pending, lits, len);
+        for (int q = tid; q < len * W; q += T) {
+            int i = q / W, w = q - i * W;
+            unsigned long long d = c.deps[(size_t)lvar(lits[i]) * W + w];
+            if (d) atomicOr(&c.sB[w], d);
+        }
+    }
+    bar();
+    // every lane analyses B (W words) the same way
+    bool zero = true, sat = false;
+    int hi1 = -1, hi2 = -1, npop = 0;
+    for (int w = W - 1; w >= 0; --w) {
+        unsigned long long x = c.sB[w];
+        zero = zero && x == 0ull;
+        if (w == W - 1) {
+            sat = (x >> 63) & 1ull;
+            x &= ~(1ull << 63);
+        }
+        if (w == 0) x &= ~1ull;
+        npop += __popcll(x);
+        while (x && hi2 < 0) {
+            int b = 63 - __clzll((long long)x);
+            int idx = w * 64 + b;
+            if (hi1 < 0) hi1 = idx; else hi2 = idx;
+            x &= ~(1ull << b);
+        }
+    }
+    zero = uni(zero ? 1 : 0) != 0;
+    sat = uni(sat ? 1 : 0) != 0;
+    hi1 = uni(hi1);
+    hi2 = uni(hi2);
+    npop = uni(npop);
+    if (zero) {
+        // the conflict follows from level-1 facts alone
+        k.conflicts += 1;
+        k.status = ST_UNSAT;
+        bar();
+        return;
+    }
+    if (a.max_conflicts >= 0 && k.conflicts >= a.max_conflicts) {
+        k.status = ST_UNKNOWN;
+        bar();
+        return;
+    }
+    k.conflicts += 1;
+    int topl, bj, nN;
+    if (sat) {
+        topl = k.cdl;
+        bj = (k.cdl - 1 >= 64 * W) ? k.cdl - 1 : (hi1 >= 0 ? hi1 + 1 : 1);
+        nN = npop + (k.cdl - 64 * W + 1);
+    } else {
+        topl = hi1 + 1;
+        bj = hi2 >= 0 ? hi2 + 1 : 1;
+        nN = npop;
+    }
+    if (hi1 + 1 > k.cdl || (sat && k.cdl < 64 * W) || topl < 2) {
+        // Deps named a level above cdl: broken invariant
+        k.status = ST_E_INTERNAL;
+        bar();
+        return;
+    }
+    if (k.n_learned + 1 > a.cap_ng || k.learned_lits + nN > a.cap_lits) {
+        k.status = ST_UNKNOWN;
+        bar();
+        return;
+    }
+    const int base = uni(c.loff[k.n_learned]);
+    const int cdl = k.cdl;
+    const int newid = k.nS + k.n_learned;
+    k.hash = fnv(k.hash, 2);
+    k.hash = fnv(k.hash, k.pend_kind == 1 ? k.pending : -1);
+    k.hash = fnv(k.hash, nN);
+    k.hash = fnv(k.hash, bj);
+    bar();
+    c.loff[k.n_learned + 1] = base + nN;
+    // the learned nogood: the decision literal of every level in levels(B),
+    // by increasing level
+    for (int w = tid; w < W; w += T) {
+        int pos = 0;
+        for (int w2 = 0; w2 < w; ++w2) {
+            unsigned long long y = c.sB[w2];
+            if (w2 == W - 1) y &= ~(1ull << 63);
+            if (w2 == 0) y &= ~1ull;
+            pos += __popcll(y);
+        }
+        unsigned long long x = c.sB[w];
+        if (w == W - 1) x &= ~(1ull << 63);
+        if (w == 0) x &= ~1ull;
+        while (x) {
+            int b = __ffsll((long long)x) - 1;
+            x &= x - 1ull;
+            c.llits[base + pos] = c.dec[w * 64 + b + 1];
+            ++pos;
+        }
+    }
+    if (sat)
+        for (int l = 64 * W + tid; l <= cdl; l += T) c.llits[base + npop + (l - 64 * W)] = c.dec[l];
+    __threadfence();
+    bar();
+    // literal occurrence lists of the new nogood (one lane per literal; the
+    // literals are distinct): doubling arrays in the slot's pool
+    for (int i = tid; i < nN; i += T) {
+        int li = lidx(c.llits[base + i]);
+        int n = c.ln[li], cap = c.lcap[li], p = c.lptr[li];
+        if (n == cap) {
+            int ncap = cap ? 2 * cap : 4;
+            int np = atomicAdd(&c.scr->pool_top, ncap);
+            if ((int64_t)np + ncap > c.pool_cap) {
+                c.scr->cap_err = 1;
+                continue;
+            }
+            for (int q = 0; q < n; ++q) c.pool[np + q] = c.pool[p + q];
+            c.lptr[li] = np;
+            c.lcap[li] = ncap;
+            p = np;
+        }
+        c.pool[p + n] = newid;
+        c.ln[li] = n + 1;
+    }
+    // Backjump: unassign every variable above level bj (the trail holds
+    // levels in non-decreasing order, level l starting at tlim[l])
+    const int start = uni(c.tlim[bj + 1]);
+    for (int i = start + tid; i < k.qt; i += T) {
+        int v = c.trail[i];
+        vclr(c.valb, v);
+        c.lvl[v] = 0;
+        for (int w = 0; w < W; ++w) c.deps[(size_t)v * W + w] = 0ull;
+    }
+    __threadfence();
+    bar();
+    k.pool_top = uni(c.scr->pool_top);
+    if (uni(c.scr->cap_err)) {
+        k.status = ST_E_CAPACITY;
+        bar();
+        return;
+    }
+    // assert the complement of the latest decision at level bj, its Deps
+    // being those of the other decisions of the learned nogood
+    for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
+    bar();
+    for (int q = tid; q < (nN - 1) * W; q += T) {
+        int i = q / W, w = q - i * W;
+        unsigned long long d = c.deps[(size_t)lvar(c.llits[base + i]) * W + w];
+        if (d) atomicOr(&c.sB[w], d);
+    }
+    bar();
+    const int top = uni(c.llits[base + nN - 1]);
+    const int x = lvar(top);
+    for (int w = tid; w < W; w += T) c.deps[(size_t)x * W + w] = c.sB[w];
+    vset(c.valb, x, top > 0 ? VF : VT);   // identical from every lane
+    c.lvl[x] = bj;
+    c.trail[start] = x;
+    __threadfence();
+    bar();
+    for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
+    bar();
+    k.cdl = bj;
+    k.qh = start;
+    k.qt = start + 1;
+    k.pending = -1;
+    k.pend_kind = 0;
+    k.n_learned += 1;
+    k.learned_lits += nN;
+    k.learned += 1;
+    k.learned_len += nN;
+}
+
+// Decision (Sect. 2): among rules with unassigned head, T t_r and not F n_r,
+// the highest occurrence count of the head wins, ties to the lowest rule;
+// T b_r is assigned at a new level.  Without a candidate,
+// CompleteAssignment falsifies every unassigned atom.
+DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
+    const int T = c.T, tid = c.tid, W = c.W, A = k.A, Rh = k.Rh;
+    unsigned long long best = 0ull;
+    for (int j = tid; j < Rh; j += T) {
+        int p = c.RH[j];
+        if (vget(c.valb, p) != 0u) continue;
+        int t = A + 3 * j + 2;
+        if (vget(c.valb, t) != VT || vget(c.valb, t + 1) == VF) continue;
+        unsigned long long key = ((unsigned long long)(uint32_t)c.RO[j] << 32) |
+                                 (unsigned long long)(0xffffffffu - (uint32_t)j);
+        best = key > best ? key : best;
+    }
+    best = block_max_u64(c, best);
+    bar();
+    if (best != 0ull) {
+        const int j = (int)(0xffffffffu - (uint32_t)(best & 0xffffffffull));
+        const int b = A + 3 * j + 1;
+        const int ncdl = k.cdl + 1;
+        const int bit = level_bit(ncdl, W);
+        for (int w = tid; w < W; w += T)
+            c.deps[(size_t)b * W + w] = (w == (bit >> 6)) ? (1ull << (bit & 63)) : 0ull;
+        c.tlim[ncdl] = k.qt;                 // identical stores from every lane
+        c.dec[ncdl] = b;
+        c.lvl[b] = ncdl;
+        c.trail[k.qt] = b;
+        vset(c.valb, b, VT);
+        __threadfence();
+        bar();
+        k.cdl = ncdl;
+        k.qh = k.qt;
+        k.qt = k.qt + 1;
+        k.decisions += 1;
+        k.hash = fnv(k.hash, 1);
+        k.hash = fnv(k.hash, j);
+        return STEP_DECIDE;
+    }
+    // CompleteAssignment
+    const int cdl = k.cdl;
+    c.scr->tail = k.qt;
+    bar();
+    for (int p = 1 + tid; p <= A; p += T) {
+        if (vget(c.valb, p) != 0u) continue;
+        for (int w = 0; w < W; ++w) c.deps[(size_t)p * W + w] = alldec_word(w, cdl, W);
+        c.lvl[p] = cdl;
+        int pos = atomicAdd(&c.scr->tail, 1);
+        c.trail[pos] = p;
+    }
+    __threadfence();
+    bar();
+    const int nt = uni(c.scr->tail);
+    for (int i = k.qt + tid; i < nt; i += T) vset(c.valb, c.trail[i], VF);
+    bar();
+    const int n = nt - k.qt;
+    k.completes += 1;
+    k.hash = fnv(k.hash, 3);
+    k.hash = fnv(k.hash, n);
+    k.qh = k.qt;
+    k.qt = nt;
+    if (n == 0) k.status = ST_E_INTERNAL;
+    return STEP_COMPLETE;
+}
+
+// Stability check of a total assignment: M = true atoms must equal the
+// least model of the reduct (rules whose body- misses M, body- dropped).
+// Otherwise the unfounded set U = M \ LM gives the conflict: its least atom
+// u with every external support (head in U, body+ disjoint from U), whose
+// b_r is false in M.
+DEV void step_gate(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model) {
+    const int T = c.T, tid = c.tid, W = c.W, A = k.A, Rh = k.Rh;
+    uint32_t* lm = c.pendb;   // 1 bit per atom; the pending map is idle here
+    for (;;) {
+        c.scr->changed = 0;
+        bar();
+        for (int j = tid; j < Rh; j += T) {
+            int h = c.RH[j];
+            if ((lm[h >> 5] >> (h & 31)) & 1u) continue;
+            bool ok = true;
+            for (int q = c.RBO[j]; ok && q < c.RBO[j + 1]; ++q) {
+                int l = c.RBL[q];
+                if (l < 0) ok = vget(c.valb, -l) != VT;
+                else ok = (lm[l >> 5] >> (l & 31)) & 1u;
+            }
+            if (ok) {
+                atomicOr(&lm[h >> 5], 1u << (h & 31));
+                c.scr->changed = 1;
+            }
+        }
+        bar();
+        const int ch = uni(c.scr->changed);
+        bar();
+        if (!ch) break;
+    }
+    int u = 0x7fffffff;
+    for (int p = 1 + tid; p <= A; p += T) {
+        bool inM = vget(c.valb, p) == VT, inLM = (lm[p >> 5] >> (p & 31)) & 1u;
+        if (inM && !inLM) {
+            u = p;
+            break;
+        }
+    }
+    u = block_min_i32(c, u);
+    if (u == 0x7fffffff) {
+        for (int p = 1 + tid; p <= A; p += T)
+            model[p - 1] = vget(c.valb, p) == VT ? (uint8_t)1 : (uint8_t)0;
+    } else {
+        for (int w = tid; w < W; w += T)
+            c.sB[w] = a.gate_mode == 1 ? alldec_word(w, k.cdl, W) : c.deps[(size_t)u * W + w];
+        bar();
+        if (a.gate_mode == 0) {
+            for (int j = tid; j < Rh; j += T) {
+                int h = c.RH[j];
+                bool hU = vget(c.valb, h) == VT && !((lm[h >> 5] >> (h & 31)) & 1u);
+                if (!hU) continue;
+                bool ext = true;
+                for (int q = c.RBO[j]; ext && q < c.RBO[j + 1]; ++q) {
+                    int l = c.RBL[q];
+                    if (l > 0) ext = !(vget(c.valb, l) == VT && !((lm[l >> 5] >> (l & 31)) & 1u));
+                }
+                if (!ext) continue;
+                int b = A + 3 * j + 1;
+                for (int w = 0; w < W; ++w) {
+                    unsigned long long d = c.deps[(size_t)b * W + w];
+                    if (d) atomicOr(&c.sB[w], d);
+                }
+            }
+        }
+    }
+    __threadfence();
+    bar();
+    const int words = (k.V + 1 + 15) >> 4;
+    for (int i = tid; i < words; i += T) lm[i] = 0u;
+    bar();
+    if (u == 0x7fffffff) {
+        k.status = ST_SAT;
+    } else {
+        k.gate_fail += 1;
+        k.pend_kind = 2;
+        k.pending = -1;
+    }
+}
+
+// Run the state machine until the search ends, the step budget is used, or
+// the next step is not allowed (step kernels).
+DEV void run_search(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model, uint64_t t0) {
+    for (;;) {
+        int halt = 0;
+        if (k.status == ST_RUNNING) {
+            if (a.mode == MODE_STEPS) {
+                if (k.steps >= a.max_steps) halt = 1;
+            } else if (a.max_steps >= 0 && k.steps >= a.max_steps) {
+                k.status = ST_E_INTERNAL;
+            }
+            // the clock is read per wave; the workgroup acts on the OR
+            int late = (a.max_ticks && (uint64_t)(wall_clock64() - t0) > a.max_ticks) ? 1 : 0;
+            if (block_any(c, late)) k.status = ST_E_TIMEOUT;
+        }
+        int kind = STEP_DONE;
+        if (!halt && k.status == ST_RUNNING) {
+            if (!k.init_done) kind = STEP_INIT;
+            else if (k.pend_kind) kind = STEP_LEARN;
+            else if (k.qt > k.qh) kind = STEP_ROUND;
+            else if (k.qt == k.V) kind = STEP_GATE;
+            else kind = STEP_DECIDE;
+            if (a.mode == MODE_STEPS) {
+                int allowed = a.step_mask;
+                bool ok = (allowed >> kind) & 1;
+                if (kind == STEP_DECIDE) ok = ok || ((allowed >> STEP_COMPLETE) & 1);
+                if (!ok) kind = STEP_DONE;
+            }
+        }
+        kind = uni(kind);
+        if (kind == STEP_DONE) break;
+        switch (kind) {
+        case STEP_INIT: step_init(c, k); break;
+        case STEP_ROUND: step_round(c, k); break;
+        case STEP_LEARN: step_learn(c, k, a); break;
+        case STEP_GATE: step_gate(c, k, a, model); break;
+        default: kind = step_decide_or_complete(c, k); break;
+        }
+        k.steps += 1;
+        k.last_step = kind;
+        if (k.status == ST_SAT) k.hash = fnv(k.hash, 4);
+        else if (k.status == ST_UNSAT) k.hash = fnv(k.hash, 5);
+        else if (k.status == ST_UNKNOWN) k.hash = fnv(k.hash, 6);
+        bar();
+    }
+}
+
+// Every lane stores the same result values (identical stores).
+DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a) {
+    DevStats& d = a.stats[k.inst];
+    d.rounds = k.rounds;
+    d.visits = k.visits;
+    d.checks = k.checks;
+    d.props = k.props;
+    d.decisions = k.decisions;
+    d.conflicts = k.conflicts;
+    d.learned = k.learned;
+    d.learned_len = k.learned_len;
+    d.gate_fail = k.gate_fail;
+    d.completes = k.completes;
+    d.hash = k.hash;
+    d.status = k.status;
+    d.last_step = k.last_step;
+    a.verdicts[k.inst] = k.status;
+    __threadfence();
+    bar();
+}
+
+template <int MAXT>
+__global__ __launch_bounds__(MAXT) void k_search(KArgs a) {
+    HIP_DYNAMIC_SHARED(unsigned long long, smem64);  // 8-byte aligned base
+    __shared__ Scr scr;
+    Ctx c;
+    Ctl k;
+    c.W = a.W;
+    c.T = MAXT;
+    c.tid = threadIdx.x;
+    c.lane = threadIdx.x & 63;
+    c.wid = threadIdx.x >> 6;
+    c.nw = MAXT / 64;
+    c.scr = &scr;
+    c.my_visits = c.my_checks = 0ull;
+    {
+        unsigned char* p = (unsigned char*)smem64;
+        c.valb = (uint32_t*)p; p += sizeof(uint32_t) * a.words;
+        c.pendb = (uint32_t*)p; p += sizeof(uint32_t) * a.words;
+        c.sB = (unsigned long long*)p; p += sizeof(unsigned long long) * kMaxW;
+        c.sOff = (int32_t*)p; p += sizeof(int32_t) * MAXT;
+        c.sS0 = (int32_t*)p; p += sizeof(int32_t) * MAXT;
+        c.sCs = (int32_t*)p; p += sizeof(int32_t) * MAXT;
+        c.sL0 = (int32_t*)p; p += sizeof(int32_t) * MAXT;
+    }
+    const uint64_t t0 = wall_clock64();
+    if (a.mode == MODE_SOLVE) {
+        uint8_t* slot = a.slots + (size_t)blockIdx.x * a.lay.stride;
+        for (;;) {
+            // one lane of the workgroup takes the next instance: every lane
+            // runs the atomic with an increment of 1 (lane 0 of wave 0) or 0
+            int q = atomicAdd(&a.queue[0], c.tid == 0 ? 1 : 0);
+            q = __shfl(q, 0, 64);
+            bar();
+            scr.popq[c.wid] = q;
+            bar();
+            q = uni(scr.popq[0]);
+            bar();
+            const int inst = q < a.n_inst ? uni(a.order[q]) : -1;
+            if (inst < 0) break;
+            bind_instance(c, k, a, inst, slot);
+            reset_search(c, k);
+            run_search(c, k, a, a.models + a.inst[inst].model, t0);
+            flush_counters(c, k);
+            write_result(c, k, a);
+            save_ctrl(c, k);
+        }
+    } else {
+        uint8_t* slot = a.slots;
+        bind_instance(c, k, a, 0, slot);
+        if (a.mode == MODE_STEPS) {
+            load_ctrl(c, k);
+            run_search(c, k, a, a.models + a.inst[0].model, t0);
+        } else {
+            reset_search(c, k);
+        }
+        flush_counters(c, k);
+        save_ctrl(c, k);
+    }
+}
+
+__global__ void k_reset_queue(int32_t* q) {
+    if (threadIdx.x < 2) q[threadIdx.x] = 0;
+}
+
+// ------------------------------------------------------------ launchers
+size_t lds_bytes(int threads, int words) {
+    return sizeof(uint32_t) * 2 * (size_t)words + sizeof(unsigned long long) * kMaxW +
+           sizeof(int32_t) * 4 * (size_t)threads;
+}
+
+hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {
+    switch (threads) {
+    case 64: hipLaunchKernelGGL(k_search<64>, dim3(grid), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL(k_search<128>, dim3(grid), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL(k_search<256>, dim3(grid), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL(k_search<512>, dim3(grid), dim3(512), lds, s, a); break;
+    case 1024: hipLaunchKernelGGL(k_search<1024>, dim3(grid), dim3(1024), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, q);
+    return hipGetLastError();
+}
+
+static const void* search_fn(int threads) {
+    switch (threads) {
+    case 64: return (const void*)k_search<64>;
+    case 128: return (const void*)k_search<128>;
+    case 256: return (const void*)k_search<256>;
+    case 512: return (const void*)k_search<512>;
+    case 1024: return (const void*)k_search<1024>;
+    default: return nullptr;
+    }
+}
+
+hipError_t set_max_lds(int threads, size_t lds) {
+    const void* f = search_fn(threads);
+    if (!f) return hipErrorInvalidValue;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t occupancy(int threads, size_t lds, int* blocks_per_cu) {
+    const void* f = search_fn(threads);
+    if (!f) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, lds);
+}
+
+}  // namespace asp

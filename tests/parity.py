@@ -1,0 +1,52 @@
+"""Helpers that compare the HIP library with the CPU oracle (test code)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+STAT_KEYS = ("rounds", "visits", "literal_checks", "propagations", "decisions", "conflicts",
+             "learned", "learned_len", "gate_failures", "completes", "trace_hash")
+
+# oracle status -> library status
+STATUS = {oracle.RUNNING: 6, oracle.SAT: 1, oracle.UNSAT: 2, oracle.UNKNOWN: 3,
+          oracle.E_INTERNAL: -5}
+
+
+def oracle_learned(st: "oracle.State"):
+    base = int(st.ng_off[st.n_static])
+    off = st.ng_off[st.n_static:] - base
+    return off.astype(np.int32), st.ng_lits[base:].astype(np.int32)
+
+
+def to_lib_state(st: "oracle.State", stats: dict):
+    from paper_1909_01786_amd.binding import State
+    off, lits = oracle_learned(st)
+    return State(st.V, st.W, st.cdl, st.val.copy(), st.lvl.copy(), st.deps.copy(),
+                 st.dec.copy(), st.frontier.copy(), off, lits,
+                 st.pend_id if st.pend_kind == 1 else -1,
+                 1 if st.last_step != oracle.ST_NONE else 0, STATUS[st.status], dict(stats))
+
+
+def assert_same_state(o: "oracle.State", g, where=""):
+    assert g.cdl == o.cdl, (where, "cdl", g.cdl, o.cdl)
+    bad = np.nonzero(g.val != o.val)[0]
+    assert bad.size == 0, (where, "val differs at vars", bad[:10], g.val[bad[:10]], o.val[bad[:10]])
+    bad = np.nonzero(g.lvl != o.lvl)[0]
+    assert bad.size == 0, (where, "lvl differs at vars", bad[:10], g.lvl[bad[:10]], o.lvl[bad[:10]])
+    bad = np.nonzero((g.deps != o.deps).any(axis=1))[0]
+    assert bad.size == 0, (where, "deps differ at vars", bad[:10])
+    assert np.array_equal(g.dec[2:o.cdl + 1], o.dec[2:o.cdl + 1]), (where, "dec")
+    assert np.array_equal(np.sort(g.frontier), o.frontier), (where, "frontier")
+    off, lits = oracle_learned(o)
+    assert np.array_equal(g.learned_off, off), (where, "learned offsets")
+    assert np.array_equal(g.learned, lits), (where, "learned literals")
+    pend = o.pend_id if o.pend_kind == 1 else -1
+    if o.pend_kind != 2:
+        assert g.pending == pend, (where, "pending", g.pending, pend)
+
+
+def assert_same_stats(o: dict, g: dict, where=""):
+    for k in STAT_KEYS:
+        assert int(g[k]) == int(o[k]) if k != "trace_hash" else \
+            (int(g[k]) & (2 ** 64 - 1)) == (int(o[k]) & (2 ** 64 - 1)), (where, k, g[k], o[k])

@@ -101,11 +101,16 @@ DEV uint32_t lcode(int l) { return l > 0 ? VT : VF; }     // value making litera
 DEV int lvar(int l) { return l < 0 ? -l : l; }
 DEV int lidx(int l) { return 2 * lvar(l) + (l < 0 ? 1 : 0); }
 
-DEV int32_t ld_agent(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// The lowest-id implier per variable is shared only inside the workgroup:
+// workgroup-scope atomics, ordered by the barriers' workgroup fences.
+DEV int32_t ld_wg(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-DEV void st_agent(int32_t* p, int32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+DEV void st_wg(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+DEV void min_wg(int32_t* p, int32_t v) {
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 DEV uint64_t fnv(uint64_t h, int32_t w) {
@@ -278,7 +283,7 @@ DEV void reset_search(Ctx& c, Ctl& k) {
     for (int v = tid; v <= V; v += T) {
         c.lvl[v] = 0;
         c.val8[v] = 0;
-        st_agent(&c.win[v], WIN_NONE);
+        st_wg(&c.win[v], WIN_NONE);
     }
     for (int q = tid; q < (V + 1) * W; q += T) c.deps[q] = 0ull;
     for (int q = tid; q < 2 * (V + 1); q += T) {
@@ -303,7 +308,6 @@ DEV void reset_search(Ctx& c, Ctl& k) {
     k.visits = k.checks = 0;
     k.hash = FNV_BASIS;
     k.steps = 0;
-    __threadfence();
     bar();
 }
 
@@ -390,7 +394,6 @@ DEV void save_ctrl(Ctx& c, const Ctl& k) {
     g.gate_fail = k.gate_fail;
     g.completes = k.completes;
     g.hash = k.hash;
-    __threadfence();
     bar();
 }
 
@@ -418,7 +421,6 @@ DEV void step_init(Ctx& c, Ctl& k) {
             }
         }
     }
-    __threadfence();
     bar();
     const int q0 = k.qt;
     const int q1 = uni(c.scr->tail);
@@ -433,7 +435,6 @@ DEV void step_init(Ctx& c, Ctl& k) {
     }
     bar();
     for (int i = q0 + tid; i < q1; i += T) vclr(c.pendb, c.trail[i]);
-    __threadfence();
     bar();
     k.init_done = 1;
     if (clash) {
@@ -475,7 +476,7 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, int pass) {
     const int x = lvar(u);
     const uint32_t code = u > 0 ? VF : VT;   // implied value of x
     if (pass == 0) {
-        atomicMin(&c.win[x], id * 2 + (code == VF ? 1 : 0));
+        min_wg(&c.win[x], id * 2 + (code == VF ? 1 : 0));
         uint32_t sh = (uint32_t)(x & 15) << 1;
         uint32_t old = atomicOr(&c.pendb[x >> 4], code << sh);
         uint32_t ob = (old >> sh) & 3u;
@@ -486,7 +487,7 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, int pass) {
             c.scr->clash = 1;
         }
     } else {
-        int key = ld_agent(&c.win[x]);
+        int key = ld_wg(&c.win[x]);
         uint32_t wcode = (key & 1) ? VF : VT;
         if (wcode != code)
             atomicMin(&c.scr->conf_key, ((unsigned long long)(uint32_t)len << 32) | (uint32_t)id);
@@ -542,19 +543,17 @@ DEV void step_round(Ctx& c, Ctl& k) {
     c.scr->tail = qt;
     bar();
     visit_pass(c, k, qh, qt, 0);
-    __threadfence();
     bar();
     if (uni(c.scr->clash)) {
         visit_pass(c, k, qh, qt, 1);
-        __threadfence();
-        bar();
+            bar();
     }
     const int nt = uni(c.scr->tail);
     // apply every implication, its Deps being the OR of the Deps of the
     // other variables of the winning nogood (mk_dl_bitmap)
     for (int i = qt + tid; i < nt; i += T) {
         int x = c.trail[i];
-        int key = ld_agent(&c.win[x]);
+        int key = ld_wg(&c.win[x]);
         int id = key >> 1;
         uint32_t code = (key & 1) ? VF : VT;
         const int32_t* lits;
@@ -580,9 +579,8 @@ DEV void step_round(Ctx& c, Ctl& k) {
         c.lvl[x] = cdl;
         vset(c.valb, x, code);
         vclr(c.pendb, x);
-        st_agent(&c.win[x], WIN_NONE);
+        st_wg(&c.win[x], WIN_NONE);
     }
-    __threadfence();
     bar();
     const unsigned long long ck = (unsigned long long)uni64((int64_t)c.scr->conf_key);
     bar();
@@ -704,7 +702,6 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     }
     if (sat)
         for (int l = 64 * W + tid; l <= cdl; l += T) c.llits[base + npop + (l - 64 * W)] = c.dec[l];
-    __threadfence();
     bar();
     // literal occurrence lists of the new nogood (one lane per literal; the
     // literals are distinct): doubling arrays in the slot's pool
@@ -735,7 +732,6 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
         c.lvl[v] = 0;
         for (int w = 0; w < W; ++w) c.deps[(size_t)v * W + w] = 0ull;
     }
-    __threadfence();
     bar();
     k.pool_top = uni(c.scr->pool_top);
     if (uni(c.scr->cap_err)) {
@@ -759,7 +755,6 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     vset(c.valb, x, top > 0 ? VF : VT);   // identical from every lane
     c.lvl[x] = bj;
     c.trail[start] = x;
-    __threadfence();
     bar();
     for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
     bar();
@@ -804,8 +799,7 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         c.lvl[b] = ncdl;
         c.trail[k.qt] = b;
         vset(c.valb, b, VT);
-        __threadfence();
-        bar();
+            bar();
         k.cdl = ncdl;
         k.qh = k.qt;
         k.qt = k.qt + 1;
@@ -825,7 +819,6 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         int pos = atomicAdd(&c.scr->tail, 1);
         c.trail[pos] = p;
     }
-    __threadfence();
     bar();
     const int nt = uni(c.scr->tail);
     for (int i = k.qt + tid; i < nt; i += T) vset(c.valb, c.trail[i], VF);
@@ -905,7 +898,6 @@ DEV void step_gate(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model) {
             }
         }
     }
-    __threadfence();
     bar();
     const int words = (k.V + 1 + 15) >> 4;
     for (int i = tid; i < words; i += T) lm[i] = 0u;
@@ -983,7 +975,6 @@ DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a) {
     d.status = k.status;
     d.last_step = k.last_step;
     a.verdicts[k.inst] = k.status;
-    __threadfence();
     bar();
 }
 

@@ -1,6 +1,6 @@
 """Benchmark of the batched GPU search (one MI355X).
 
-One step = one persistent launch (asp_solve_batch) that runs the whole
+One step = one batched solve (asp_solve_batch) that runs the whole
 search -- InitialPropagation, PropagateAndCheck rounds, Fwd-learning with
 Backjump, Decision / CompleteAssignment and the stability check -- for every
 program of a batch of uneven random ground programs (4096 programs, atoms
@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--budget", type=int, default=2000, help="conflicts per instance")
     ap.add_argument("--W", type=int, default=1)
     ap.add_argument("--threads", type=int, default=128)
-    ap.add_argument("--wg-per-cu", type=int, default=4)
+    ap.add_argument("--classes", type=int, default=4, help="LDS size classes (launches)")
     ap.add_argument("--cap-ng", type=int, default=4096)
     ap.add_argument("--cap-lits", type=int, default=1 << 18)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -155,7 +155,7 @@ def main():
         f"{n_lits} nogood literals")
 
     stream = torch.cuda.Stream(device=dev)
-    batch = P.Batch(gp, threads=args.threads, wg_per_cu=args.wg_per_cu)
+    batch = P.Batch(gp, threads=args.threads, classes=args.classes)
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
         batch.bind(dev, stream=stream)
@@ -209,7 +209,7 @@ def main():
                         f"(atoms log-uniform 100..5000, rules/atoms 2..4, bodies 1..4, 50% negative), "
                         f"conflict budget {args.budget}, W={args.W}",
             "instances": args.n, "nogood_literals": n_lits, "threads_per_wg": args.threads,
-            "wg_per_cu": args.wg_per_cu, "budget_conflicts": args.budget,
+            "lds_classes": args.classes, "budget_conflicts": args.budget,
         },
         "instances_per_s": (n_sat + n_unsat) / (ms_step / 1000.0),
         "verdicts": {"sat": n_sat, "unsat": n_unsat, "unknown": n_unknown, "error": n_err},

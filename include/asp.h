@@ -86,15 +86,20 @@ typedef struct {
 /* Run limits. */
 typedef struct {
     int64_t max_conflicts;     /* <0 = unlimited; reaching it -> ASP_UNKNOWN */
-    int64_t max_ms;            /* device wall-clock guard per launch, <=0 none;
-                                  firing gives ASP_E_TIMEOUT for the instances
-                                  still open */
+    int64_t max_ms;            /* device wall-clock guard per launch; <=0 takes
+                                  the default of 600000 ms (every launch is
+                                  bounded); firing gives ASP_E_TIMEOUT for the
+                                  instances still open */
 } asp_limits;
 
 /* Launch schedule (no effect on results). */
 typedef struct {
     int32_t threads;           /* threads per workgroup: 64, 128, 256, 512 or 1024 */
-    int32_t wg_per_cu;         /* persistent workgroups per compute unit, >= 1 */
+    int32_t classes;           /* batches: LDS size classes by variable count,
+                                  1..4; each class is one launch on its own
+                                  stream, with LDS sized for its largest
+                                  instance (more classes: more resident
+                                  workgroups) */
 } asp_schedule;
 
 /* Search counters (the paper's Fig. 1/2 metrics plus literal checks).
@@ -224,11 +229,13 @@ int32_t asp_state_import(asp_program *prog, void *stream, const asp_state *st);
 
 /* ------------------------------------------------------------ batches */
 
-/* Plan one persistent launch over n programs (all loaded with the same W and
- * gate option).  The programs must stay alive until asp_batch_bind returns.
- * sched: NULL = {64 threads, 8 workgroups per CU}.  *device_bytes gets the
- * arena size; *model_bytes (optional) the size of the model output, which
- * holds instance i's n_atoms bytes after those of instances 0..i-1. */
+/* Plan the batched solve of n programs (all loaded with the same options):
+ * one workgroup per instance, instances grouped by LDS size class, largest
+ * first inside a class, and one search-state slot per instance.  The
+ * programs must stay alive until asp_batch_bind returns.
+ * sched: NULL = {128 threads, 4 classes}.  *device_bytes gets the arena
+ * size; *model_bytes (optional) the size of the model output, which holds
+ * instance i's n_atoms bytes after those of instances 0..i-1. */
 int32_t asp_batch_create(int32_t n, asp_program *const *progs,
                          const asp_schedule *sched, asp_batch **out,
                          uint64_t *device_bytes, uint64_t *model_bytes);
@@ -237,9 +244,10 @@ int32_t asp_batch_create(int32_t n, asp_program *const *progs,
 int32_t asp_batch_bind(asp_batch *batch, void *dev_arena, uint64_t bytes,
                        void *stream);
 
-/* Enqueue the batched solve on stream (asynchronous): one persistent launch
- * in which each workgroup takes the largest open instance from a queue and
- * solves it to a verdict.  Results stay in the arena. */
+/* Enqueue the batched solve on stream (asynchronous): one launch per LDS
+ * class, forked onto internal streams after the work already on `stream`
+ * and joined back into it; each workgroup solves one instance to a verdict.
+ * Results stay in the arena. */
 int32_t asp_solve_batch(asp_batch *batch, void *stream, const asp_limits *lim);
 
 /* Copy verdicts[n] (ASP_SAT/UNSAT/UNKNOWN or a negative error),
@@ -247,8 +255,8 @@ int32_t asp_solve_batch(asp_batch *batch, void *stream, const asp_limits *lim);
 int32_t asp_batch_results(asp_batch *batch, void *stream, int32_t *verdicts,
                           uint8_t *models, asp_stats *stats);
 
-/* Kernel-only timing of the last asp_solve_batch launch, in milliseconds,
- * measured with HIP events recorded on the launch stream. */
+/* Device time of the last asp_solve_batch, in milliseconds, between HIP
+ * events recorded on the caller's stream around the forked launches. */
 int32_t asp_batch_last_ms(asp_batch *batch, double *ms);
 
 int32_t asp_batch_free(asp_batch *batch);

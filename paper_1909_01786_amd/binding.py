@@ -37,7 +37,7 @@ class asp_limits(C.Structure):
 
 
 class asp_schedule(C.Structure):
-    _fields_ = [("threads", C.c_int32), ("wg_per_cu", C.c_int32)]
+    _fields_ = [("threads", C.c_int32), ("classes", C.c_int32)]
 
 
 _STAT_NAMES = ("rounds", "visits", "literal_checks", "propagations", "decisions", "conflicts",
@@ -296,13 +296,14 @@ class Program:
 
 
 class Batch:
-    """Many programs solved by one persistent launch (asp_solve_batch)."""
+    """Many programs solved together (asp_solve_batch): one workgroup per
+    program, one launch per LDS size class."""
 
-    def __init__(self, programs, threads: int = 64, wg_per_cu: int = 8):
+    def __init__(self, programs, threads: int = 128, classes: int = 4):
         self.programs = list(programs)
         arr = (C.c_void_p * len(self.programs))(*[p._h.value for p in self.programs])
         self._arr = arr
-        sch = asp_schedule(int(threads), int(wg_per_cu))
+        sch = asp_schedule(int(threads), int(classes))
         h = C.c_void_p()
         nb, mb = C.c_uint64(0), C.c_uint64(0)
         _check(lib().asp_batch_create(len(self.programs), C.cast(arr, C.c_void_p), C.byref(sch),

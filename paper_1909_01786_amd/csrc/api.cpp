@@ -22,7 +22,6 @@
 namespace asp {
 size_t lds_bytes(int threads, int words);
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s);
-hipError_t launch_reset_queue(int32_t* q, hipStream_t s);
 hipError_t set_max_lds(int threads, size_t lds);
 hipError_t occupancy(int threads, size_t lds, int* blocks_per_cu);
 }  // namespace asp
@@ -74,19 +73,30 @@ bool valid_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 |
 }  // namespace
 
 // ---------------------------------------------------------------- handles
-struct Plan {
-    int32_t n = 0, threads = 256, grid = 1, W = 1, gate = 0;
-    int64_t Vmax = 0, Rhmax = 0, cap_ng = 0, cap_lits = 0;
-    int32_t words = 1;
+// One launch of the search kernel: instances order[first .. first+count),
+// LDS sized for the largest of them.
+struct LaunchClass {
+    int32_t first = 0, count = 0, words = 1;
     size_t lds = 0;
-    SlotLayout lay{};
-    uint64_t off_desc = 0, off_order = 0, off_ngo = 0, off_ngl = 0, off_mo = 0, off_mi = 0,
-             off_rh = 0, off_ro = 0, off_rbo = 0, off_rbl = 0, off_verd = 0, off_stats = 0,
-             off_models = 0, off_queue = 0, off_slots = 0, total = 0;
+};
+
+struct Plan {
+    int32_t n = 0, threads = 256, W = 1, gate = 0;
+    int64_t Vmax = 0, Rhmax = 0, cap_ng = 0, cap_lits = 0;
+    std::vector<LaunchClass> classes;
     std::vector<InstDesc> desc;
     std::vector<int32_t> order;
+    std::vector<int64_t> slot_off;      // per instance, bytes from off_slots
+    uint64_t off_desc = 0, off_order = 0, off_slotoff = 0, off_ngo = 0, off_ngl = 0, off_mo = 0,
+             off_mi = 0, off_rh = 0, off_ro = 0, off_rbo = 0, off_rbl = 0, off_verd = 0,
+             off_stats = 0, off_models = 0, off_slots = 0, total = 0;
     int64_t tot_ngo = 0, tot_ngl = 0, tot_mo = 0, tot_mi = 0, tot_rules = 0, tot_rbo = 0,
-            tot_rbl = 0, tot_model = 0;
+            tot_rbl = 0, tot_model = 0, slots_bytes = 0;
+    size_t max_lds() const {
+        size_t m = 0;
+        for (auto& c : classes) m = std::max(m, c.lds);
+        return m;
+    }
 };
 
 struct asp_program {
@@ -106,11 +116,16 @@ struct asp_batch {
     Plan plan;
     bool bound = false;
     uint8_t* arena = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_fork = nullptr;
+    std::vector<hipStream_t> streams;    // one per launch class (default priority)
+    std::vector<hipEvent_t> ev_join;
     bool timed = false;
 };
 
 namespace {
+
+// Wall-clock guard applied when the caller gives none: every launch ends.
+constexpr int64_t kDefaultMaxMs = 600000;
 
 asp_options default_options() {
     asp_options o;
@@ -121,38 +136,18 @@ asp_options default_options() {
     return o;
 }
 
-void slot_layout(Plan& P) {
-    SlotLayout& L = P.lay;
-    uint64_t o = 0;
-    auto take = [&](uint64_t bytes) {
-        uint64_t at = o;
-        o = align_up(o + bytes);
-        return (int64_t)at;
-    };
-    const uint64_t V1 = (uint64_t)P.Vmax + 1, R3 = (uint64_t)P.Rhmax + 3;
-    L.ctrl = take(sizeof(SlotCtrl));
-    L.val8 = take(V1);
-    L.lvl = take(4 * V1);
-    L.deps = take(8 * V1 * (uint64_t)P.W);
-    L.win = take(4 * V1);
-    L.trail = take(4 * V1);
-    L.tlim = take(4 * R3);
-    L.dec = take(4 * R3);
-    L.locc_ptr = take(8 * V1);
-    L.locc_n = take(8 * V1);
-    L.locc_cap = take(8 * V1);
-    L.l_off = take(4 * ((uint64_t)P.cap_ng + 1));
-    L.l_lits = take(4 * (uint64_t)P.cap_lits);
-    // doubling occurrence arrays: every list of n entries has used at most
-    // 4n + 8 entries; learned nogoods hold only decision literals T b_r, so
-    // at most Rh lists exist
-    L.pool_cap = 4 * P.cap_lits + 8 * (P.Rhmax + 1);
-    L.pool = take(4 * (uint64_t)L.pool_cap);
-    L.stride = (int64_t)o;
+// LDS size classes by variable count (the 2-bit maps take V/4 bytes each).
+std::vector<int64_t> class_bounds(int32_t classes) {
+    switch (classes) {
+    case 1: return {};
+    case 2: return {16383};
+    case 3: return {8191, 32767};
+    default: return {4095, 16383, 32767};
+    }
 }
 
 int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_options& opt,
-                  int32_t threads, int32_t grid, Plan& P) {
+                  int32_t threads, int32_t n_classes, Plan& P) {
     P = Plan();
     P.n = (int32_t)progs.size();
     P.threads = threads;
@@ -161,6 +156,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.cap_ng = opt.learned_cap_ng;
     P.cap_lits = opt.learned_cap_lits;
     P.desc.resize(P.n);
+    P.slot_off.resize(P.n);
     for (int32_t i = 0; i < P.n; ++i) {
         const HostProgram& h = *progs[i];
         InstDesc& d = P.desc[i];
@@ -192,18 +188,35 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
         P.tot_model += h.A;
         P.Vmax = std::max<int64_t>(P.Vmax, h.V);
         P.Rhmax = std::max<int64_t>(P.Rhmax, h.Rh);
+        P.slot_off[i] = P.slots_bytes;
+        P.slots_bytes += slot_layout(h.V, h.Rh, P.W, P.cap_ng, P.cap_lits).stride;
     }
+    // launch classes by variable count; largest first inside a class
+    const std::vector<int64_t> bounds = class_bounds(std::max(1, n_classes));
+    auto cls = [&](int32_t i) {
+        int c = 0;
+        while (c < (int)bounds.size() && progs[i]->V > bounds[c]) ++c;
+        return c;
+    };
     P.order.resize(P.n);
     std::iota(P.order.begin(), P.order.end(), 0);
+    auto work = [&](int32_t i) { return progs[i]->ng_lits.size() + (size_t)progs[i]->V; };
     std::stable_sort(P.order.begin(), P.order.end(), [&](int32_t a, int32_t b) {
-        const HostProgram& x = *progs[a];
-        const HostProgram& y = *progs[b];
-        return x.ng_lits.size() + (size_t)x.V > y.ng_lits.size() + (size_t)y.V;
+        int ca = cls(a), cb = cls(b);
+        if (ca != cb) return ca > cb;
+        return work(a) > work(b);
     });
-    P.grid = std::max(1, std::min(grid, std::max(P.n, 1)));
-    P.words = (int32_t)((P.Vmax + 1 + 15) / 16);
-    P.lds = lds_bytes(threads, P.words);
-    slot_layout(P);
+    for (int32_t k = 0; k < P.n;) {
+        LaunchClass lc;
+        lc.first = k;
+        const int c = cls(P.order[k]);
+        int64_t vmax = 0;
+        while (k < P.n && cls(P.order[k]) == c) vmax = std::max<int64_t>(vmax, progs[P.order[k++]]->V);
+        lc.count = k - lc.first;
+        lc.words = (int32_t)((vmax + 1 + 15) / 16);
+        lc.lds = lds_bytes(threads, lc.words);
+        P.classes.push_back(lc);
+    }
     uint64_t o = 0;
     auto take = [&](uint64_t bytes) {
         uint64_t at = o;
@@ -212,6 +225,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     };
     P.off_desc = take(sizeof(InstDesc) * (uint64_t)P.n);
     P.off_order = take(4 * (uint64_t)P.n);
+    P.off_slotoff = take(8 * (uint64_t)P.n);
     P.off_ngo = take(4 * (uint64_t)P.tot_ngo);
     P.off_ngl = take(4 * (uint64_t)P.tot_ngl);
     P.off_mo = take(4 * (uint64_t)P.tot_mo);
@@ -223,8 +237,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.off_verd = take(4 * (uint64_t)P.n);
     P.off_stats = take(sizeof(DevStats) * (uint64_t)P.n);
     P.off_models = take((uint64_t)P.tot_model + 1);
-    P.off_queue = take(64);
-    P.off_slots = take((uint64_t)P.lay.stride * (uint64_t)P.grid);
+    P.off_slots = take((uint64_t)P.slots_bytes);
     P.total = o;
     return ASP_OK;
 }
@@ -256,6 +269,7 @@ int32_t upload_static(const std::vector<const HostProgram*>& progs, const Plan& 
     std::vector<int32_t> rbl = concat(progs, &HostProgram::rb_lits);
     HIPCHK(put(P.off_desc, P.desc.data(), sizeof(InstDesc) * P.desc.size()));
     HIPCHK(put(P.off_order, P.order.data(), 4 * P.order.size()));
+    HIPCHK(put(P.off_slotoff, P.slot_off.data(), 8 * P.slot_off.size()));
     HIPCHK(put(P.off_ngo, ngo.data(), 4 * ngo.size()));
     HIPCHK(put(P.off_ngl, ngl.data(), 4 * ngl.size()));
     HIPCHK(put(P.off_mo, mo.data(), 4 * mo.size()));
@@ -268,11 +282,12 @@ int32_t upload_static(const std::vector<const HostProgram*>& progs, const Plan& 
     return ASP_OK;
 }
 
-KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode) {
+KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& lc) {
     KArgs a{};
     a.inst = (const InstDesc*)(arena + P.off_desc);
     a.order = (const int32_t*)(arena + P.off_order);
-    a.n_inst = P.n;
+    a.first = lc.first;
+    a.count = lc.count;
     a.mode = mode;
     a.ng_off = (const int32_t*)(arena + P.off_ngo);
     a.ng_lits = (const int32_t*)(arena + P.off_ngl);
@@ -283,14 +298,13 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode) {
     a.rb_off = (const int32_t*)(arena + P.off_rbo);
     a.rb_lits = (const int32_t*)(arena + P.off_rbl);
     a.slots = arena + P.off_slots;
-    a.lay = P.lay;
-    a.queue = (int32_t*)(arena + P.off_queue);
+    a.slot_off = (const int64_t*)(arena + P.off_slotoff);
     a.verdicts = (int32_t*)(arena + P.off_verd);
     a.stats = (DevStats*)(arena + P.off_stats);
     a.models = arena + P.off_models;
     a.W = P.W;
     a.gate_mode = P.gate;
-    a.words = P.words;
+    a.words = lc.words;
     a.step_mask = 0;
     a.max_steps = -1;
     a.max_conflicts = -1;
@@ -299,9 +313,6 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode) {
     a.max_ticks = 0;
     return a;
 }
-
-// Device wall-clock guard used when the caller gives none: every launch ends.
-constexpr int64_t kDefaultMaxMs = 600000;
 
 void apply_limits(KArgs& a, const Plan& P, const asp_limits* lim, const DeviceInfo& di) {
     a.max_conflicts = lim ? lim->max_conflicts : -1;
@@ -348,11 +359,11 @@ void ctrl_stats(const SlotCtrl& k, asp_stats* s) {
 
 int32_t check_launch(const Plan& P, const DeviceInfo& di) {
     if (!di.ok) return fail(ASP_E_DEVICE, "no HIP device");
-    if (P.lds > di.max_lds)
-        return fail(ASP_E_CAPACITY, "largest instance needs " + std::to_string(P.lds) +
+    if (P.max_lds() > di.max_lds)
+        return fail(ASP_E_CAPACITY, "largest instance needs " + std::to_string(P.max_lds()) +
                                         " bytes of LDS, device allows " +
                                         std::to_string(di.max_lds));
-    (void)set_max_lds(P.threads, P.lds);  // best effort: older runtimes ignore it
+    (void)set_max_lds(P.threads, P.max_lds());  // best effort: older runtimes ignore it
     return ASP_OK;
 }
 
@@ -362,16 +373,22 @@ int32_t run_single(asp_program* p, hipStream_t s, int32_t mode, int32_t mask, in
     DeviceInfo di = device_info();
     int32_t rc = check_launch(p->plan, di);
     if (rc) return rc;
-    KArgs a = make_args(p->plan, p->arena, mode);
+    const LaunchClass& lc = p->plan.classes[0];
+    KArgs a = make_args(p->plan, p->arena, mode, lc);
     apply_limits(a, p->plan, lim, di);
     a.step_mask = mask;
     a.max_steps = steps;
-    HIPCHK(launch_search(a, p->threads, 1, p->plan.lds, s));
+    HIPCHK(launch_search(a, p->threads, 1, lc.lds, s));
     HIPCHK(hipStreamSynchronize(s));
     return ASP_OK;
 }
 
-SlotCtrl* ctrl_ptr(asp_program* p) { return (SlotCtrl*)(p->arena + p->plan.off_slots + p->plan.lay.ctrl); }
+// the single program's slot (instance 0)
+SlotLayout slot0(const asp_program* p) {
+    return slot_layout(p->hp.V, p->hp.Rh, p->opt.W, p->opt.learned_cap_ng, p->opt.learned_cap_lits);
+}
+
+SlotCtrl* ctrl_ptr(asp_program* p) { return (SlotCtrl*)(p->arena + p->plan.off_slots + slot0(p).ctrl); }
 
 int32_t read_ctrl(asp_program* p, hipStream_t s, SlotCtrl* out) {
     HIPCHK(hipMemcpyAsync(out, ctrl_ptr(p), sizeof(SlotCtrl), hipMemcpyDeviceToHost, s));
@@ -534,7 +551,8 @@ int32_t asp_analyze_conflict(asp_program* p, void* stream, const asp_limits* lim
     if (e.status != ASP_RUNNING) return e.status;
     if (e.status == ASP_RUNNING && e.pend_kind != 0) return fail(ASP_E_INTERNAL, "learning did not run");
     int32_t off[2];
-    HIPCHK(hipMemcpyAsync(off, slot_arr<int32_t>(p, p->plan.lay.l_off) + (e.n_learned - 1), 8,
+    const SlotLayout L0 = slot0(p);
+    HIPCHK(hipMemcpyAsync(off, slot_arr<int32_t>(p, L0.l_off) + (e.n_learned - 1), 8,
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     int32_t len = off[1] - off[0];
@@ -542,7 +560,7 @@ int32_t asp_analyze_conflict(asp_program* p, void* stream, const asp_limits* lim
     if (backjump_level) *backjump_level = e.cdl;
     if (learned_lits) {
         if (cap < len) return fail(ASP_E_CAPACITY, "learned nogood longer than cap");
-        HIPCHK(hipMemcpyAsync(learned_lits, slot_arr<int32_t>(p, p->plan.lay.l_lits) + off[0],
+        HIPCHK(hipMemcpyAsync(learned_lits, slot_arr<int32_t>(p, L0.l_lits) + off[0],
                               4 * (size_t)len, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     }
@@ -569,10 +587,10 @@ int32_t asp_solve(asp_program* p, void* stream, const asp_limits* lim, uint8_t* 
     DeviceInfo di = device_info();
     int32_t rc = check_launch(p->plan, di);
     if (rc) return rc;
-    KArgs a = make_args(p->plan, p->arena, MODE_SOLVE);
+    const LaunchClass& lc = p->plan.classes[0];
+    KArgs a = make_args(p->plan, p->arena, MODE_SOLVE, lc);
     apply_limits(a, p->plan, lim, di);
-    HIPCHK(launch_reset_queue(a.queue, s));
-    HIPCHK(launch_search(a, p->threads, 1, p->plan.lds, s));
+    HIPCHK(launch_search(a, p->threads, 1, lc.lds, s));
     DevStats d;
     int32_t verdict = 0;
     HIPCHK(hipMemcpyAsync(&d, a.stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
@@ -602,7 +620,7 @@ int32_t asp_state_export(asp_program* p, void* stream, asp_state* st) {
     st->status = k.status;
     ctrl_stats(k, &st->stats);
     if (!st->val) return ASP_OK;
-    const SlotLayout& L = p->plan.lay;
+    const SlotLayout L = slot0(p);
     auto get = [&](void* dst, int64_t off, size_t bytes) -> hipError_t {
         if (!dst || bytes == 0) return hipSuccess;
         return hipMemcpyAsync(dst, p->arena + p->plan.off_slots + off, bytes,
@@ -700,7 +718,7 @@ int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
                 int32_t l = llits[q];
                 pool[fill[2 * (l < 0 ? -l : l) + (l < 0)]++] = nS + j;
             }
-        if ((int64_t)pool.size() > p->plan.lay.pool_cap) return fail(ASP_E_CAPACITY, "pool");
+        if ((int64_t)pool.size() > slot0(p).pool_cap) return fail(ASP_E_CAPACITY, "pool");
     }
     SlotCtrl k;
     memset(&k, 0, sizeof(k));
@@ -733,7 +751,7 @@ int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
     std::vector<int32_t> win(V + 1, 0x7fffffff);
     std::vector<int32_t> lvl(st->lvl, st->lvl + V + 1);
     hipStream_t s = (hipStream_t)stream;
-    const SlotLayout& L = p->plan.lay;
+    const SlotLayout L = slot0(p);
     auto put = [&](int64_t off, const void* src, size_t bytes) -> hipError_t {
         if (bytes == 0) return hipSuccess;
         return hipMemcpyAsync(p->arena + p->plan.off_slots + off, src, bytes,
@@ -762,9 +780,10 @@ int32_t asp_batch_create(int32_t n, asp_program* const* progs, const asp_schedul
                          asp_batch** out, uint64_t* device_bytes, uint64_t* model_bytes) {
     if (!out || n < 1 || !progs) return fail(ASP_E_INVALID, "empty batch or null output");
     *out = nullptr;
-    int32_t threads = sched ? sched->threads : 64;
-    int32_t wpc = sched ? sched->wg_per_cu : 8;
-    if (!valid_threads(threads) || wpc < 1) return fail(ASP_E_INVALID, "bad schedule");
+    int32_t threads = sched ? sched->threads : 128;
+    int32_t classes = sched ? sched->classes : 4;
+    if (!valid_threads(threads) || classes < 1 || classes > 4)
+        return fail(ASP_E_INVALID, "bad schedule");
     std::unique_ptr<asp_batch> b(new asp_batch());
     b->opt = progs[0] ? progs[0]->opt : default_options();
     for (int32_t i = 0; i < n; ++i) {
@@ -775,15 +794,7 @@ int32_t asp_batch_create(int32_t n, asp_program* const* progs, const asp_schedul
             return fail(ASP_E_INVALID, "batch programs must share their options");
         b->progs.push_back(&progs[i]->hp);
     }
-    DeviceInfo di = device_info();
-    if (!di.ok) return fail(ASP_E_DEVICE, "no HIP device");
-    Plan probe;
-    int32_t rc = make_plan(b->progs, b->opt, threads, 1, probe);
-    if (rc) return rc;
-    int occ = 0;
-    if (occupancy(threads, probe.lds, &occ) != hipSuccess || occ < 1) occ = 1;
-    int32_t grid = di.cus * std::min(wpc, occ);
-    rc = make_plan(b->progs, b->opt, threads, grid, b->plan);
+    int32_t rc = make_plan(b->progs, b->opt, threads, classes, b->plan);
     if (rc) return rc;
     if (device_bytes) *device_bytes = b->plan.total;
     if (model_bytes) *model_bytes = (uint64_t)b->plan.tot_model;
@@ -808,15 +819,39 @@ int32_t asp_solve_batch(asp_batch* b, void* stream, const asp_limits* lim) {
     DeviceInfo di = device_info();
     int32_t rc = check_launch(b->plan, di);
     if (rc) return rc;
-    KArgs a = make_args(b->plan, b->arena, MODE_SOLVE);
-    apply_limits(a, b->plan, lim, di);
+    const size_t nc = b->plan.classes.size();
     if (!b->ev0) {
         HIPCHK(hipEventCreate(&b->ev0));
         HIPCHK(hipEventCreate(&b->ev1));
+        HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     }
-    HIPCHK(launch_reset_queue(a.queue, s));
+    while (nc > 1 && b->streams.size() < nc) {
+        hipStream_t t;
+        hipEvent_t e;
+        HIPCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->streams.push_back(t);
+        b->ev_join.push_back(e);
+    }
     HIPCHK(hipEventRecord(b->ev0, s));
-    HIPCHK(launch_search(a, b->plan.threads, b->plan.grid, b->plan.lds, s));
+    if (nc == 1) {
+        KArgs a = make_args(b->plan, b->arena, MODE_SOLVE, b->plan.classes[0]);
+        apply_limits(a, b->plan, lim, di);
+        HIPCHK(launch_search(a, b->plan.threads, b->plan.classes[0].count, b->plan.classes[0].lds, s));
+    } else {
+        // fork: every class launches on its own stream once the caller's
+        // stream has reached this point; join back before ev1
+        HIPCHK(hipEventRecord(b->ev_fork, s));
+        for (size_t c = 0; c < nc; ++c) {
+            const LaunchClass& lc = b->plan.classes[c];
+            KArgs a = make_args(b->plan, b->arena, MODE_SOLVE, lc);
+            apply_limits(a, b->plan, lim, di);
+            HIPCHK(hipStreamWaitEvent(b->streams[c], b->ev_fork, 0));
+            HIPCHK(launch_search(a, b->plan.threads, lc.count, lc.lds, b->streams[c]));
+            HIPCHK(hipEventRecord(b->ev_join[c], b->streams[c]));
+        }
+        for (size_t c = 0; c < nc; ++c) HIPCHK(hipStreamWaitEvent(s, b->ev_join[c], 0));
+    }
     HIPCHK(hipEventRecord(b->ev1, s));
     b->timed = true;
     return ASP_OK;
@@ -858,6 +893,9 @@ int32_t asp_batch_free(asp_batch* b) {
     if (b) {
         if (b->ev0) (void)hipEventDestroy(b->ev0);
         if (b->ev1) (void)hipEventDestroy(b->ev1);
+        if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+        for (hipEvent_t e : b->ev_join) (void)hipEventDestroy(e);
+        for (hipStream_t t : b->streams) (void)hipStreamDestroy(t);
         delete b;
     }
     return ASP_OK;

@@ -4,9 +4,8 @@
 //   [static]  per-instance descriptors, the instance order, and every
 //             instance's completion nogoods (CSR), literal->nogood map (CSR),
 //             rule table and rule bodies, packed one instance after another;
-//   [results] verdicts, per-instance counters, model bytes, queue counters;
-//   [slots]   one dynamic search state per persistent workgroup, reused by
-//             every instance that workgroup solves.
+//   [results] verdicts, per-instance counters, model bytes;
+//   [slots]   one dynamic search state per instance, sized for it.
 //
 // Variables are 1..V (0 unused).  Literal index of literal l is 2*|l| + (l<0).
 #pragma once
@@ -46,25 +45,54 @@ struct SlotCtrl {
     uint64_t pend_B[kMaxW];           // gate conflict bitmap awaiting learning
 };
 
-// Element offsets of each array inside one slot (bytes for val8).
+// Byte offsets of each array inside one instance's state slot.
 struct SlotLayout {
-    int64_t ctrl;       // bytes
-    int64_t val8;       // bytes, int8[Vmax+1]
-    int64_t lvl;        // bytes, int32[Vmax+1]
-    int64_t deps;       // bytes, uint64[(Vmax+1)*W]
-    int64_t win;        // bytes, int32[Vmax+1]
-    int64_t trail;      // bytes, int32[Vmax+1]
-    int64_t tlim;       // bytes, int32[Rhmax+3]
-    int64_t dec;        // bytes, int32[Rhmax+3]
-    int64_t locc_ptr;   // bytes, int32[2(Vmax+1)]
-    int64_t locc_n;     // bytes, int32[2(Vmax+1)]
-    int64_t locc_cap;   // bytes, int32[2(Vmax+1)]
-    int64_t l_off;      // bytes, int32[cap_ng+1]
-    int64_t l_lits;     // bytes, int32[cap_lits]
-    int64_t pool;       // bytes, int32[pool_cap]
-    int64_t stride;     // bytes per slot
+    int64_t ctrl;       // SlotCtrl
+    int64_t val8;       // int8[V+1]
+    int64_t lvl;        // int32[V+1]
+    int64_t deps;       // uint64[(V+1)*W]
+    int64_t win;        // int32[V+1]
+    int64_t trail;      // int32[V+1]
+    int64_t tlim;       // int32[Rh+3]
+    int64_t dec;        // int32[Rh+3]
+    int64_t locc_ptr;   // int32[2(V+1)]
+    int64_t locc_n;     // int32[2(V+1)]
+    int64_t locc_cap;   // int32[2(V+1)]
+    int64_t l_off;      // int32[cap_ng+1]
+    int64_t l_lits;     // int32[cap_lits]
+    int64_t pool;       // int32[pool_cap]
+    int64_t stride;     // bytes of the slot
     int64_t pool_cap;   // entries
 };
+
+// Slot of an instance with V variables and Rh headed rules.  The learned
+// nogoods hold only decision literals T b_r, so at most Rh occurrence lists
+// exist; a doubling list of n entries has used at most 4n + 8 pool entries.
+__host__ __device__ inline SlotLayout slot_layout(int64_t V, int64_t Rh, int32_t W,
+                                                  int64_t cap_ng, int64_t cap_lits) {
+    SlotLayout L;
+    int64_t o = 0;
+    const int64_t V1 = V + 1, R3 = Rh + 3;
+#define ASP_TAKE(field, bytes) do { L.field = o; o = (o + (bytes) + kAlign - 1) / kAlign * kAlign; } while (0)
+    ASP_TAKE(ctrl, (int64_t)sizeof(SlotCtrl));
+    ASP_TAKE(val8, V1);
+    ASP_TAKE(lvl, 4 * V1);
+    ASP_TAKE(deps, 8 * V1 * W);
+    ASP_TAKE(win, 4 * V1);
+    ASP_TAKE(trail, 4 * V1);
+    ASP_TAKE(tlim, 4 * R3);
+    ASP_TAKE(dec, 4 * R3);
+    ASP_TAKE(locc_ptr, 8 * V1);
+    ASP_TAKE(locc_n, 8 * V1);
+    ASP_TAKE(locc_cap, 8 * V1);
+    ASP_TAKE(l_off, 4 * (cap_ng + 1));
+    ASP_TAKE(l_lits, 4 * cap_lits);
+    L.pool_cap = 4 * cap_lits + 8 * (Rh + 1);
+    ASP_TAKE(pool, 4 * L.pool_cap);
+#undef ASP_TAKE
+    L.stride = o;
+    return L;
+}
 
 struct DevStats {
     int64_t rounds, visits, checks, props, decisions, conflicts, learned, learned_len,
@@ -79,9 +107,9 @@ enum StepKind : int32_t {
 };
 
 enum Mode : int32_t {
-    MODE_SOLVE = 0,      // persistent: pop instances, solve each to a verdict
-    MODE_STEPS = 1,      // slot 0, instance 0: run up to max_steps steps
-    MODE_RESET = 2,      // slot 0, instance 0: fresh search state
+    MODE_SOLVE = 0,      // workgroup b solves instance order[first + b] to a verdict
+    MODE_STEPS = 1,      // instance 0: run up to max_steps steps
+    MODE_RESET = 2,      // instance 0: fresh search state
 };
 
 // Status values (match asp.h).
@@ -92,9 +120,10 @@ enum : int32_t {
 
 struct KArgs {
     const InstDesc* inst;
-    const int32_t* order;        // instance ids, largest first
-    int32_t n_inst;
+    const int32_t* order;        // instance ids grouped by LDS class, largest first
+    int32_t first, count;        // this launch: order[first .. first+count)
     int32_t mode;
+    int32_t pad0;
     const int32_t* ng_off;
     const int32_t* ng_lits;
     const int32_t* map_off;
@@ -103,14 +132,13 @@ struct KArgs {
     const int32_t* rule_occ;
     const int32_t* rb_off;
     const int32_t* rb_lits;
-    uint8_t* slots;
-    SlotLayout lay;
-    int32_t* queue;              // [0] next order index, [1] finished count
+    uint8_t* slots;              // base of the state slots
+    const int64_t* slot_off;     // byte offset of each instance's slot
     int32_t* verdicts;
     DevStats* stats;
     uint8_t* models;
     int32_t W, gate_mode;
-    int32_t words;               // LDS words per 2-bit bitmap (Vmax+1 vars)
+    int32_t words;               // LDS words per 2-bit map (this launch's largest V)
     int32_t step_mask;           // MODE_STEPS: kinds allowed to run (bit k)
     int64_t max_steps;           // MODE_STEPS: steps to run; MODE_SOLVE: guard
     int64_t max_conflicts;       // <0 unlimited

@@ -4,8 +4,8 @@
 // the paper): InitialPropagation, PropagateAndCheck rounds (Sect. 4.1),
 // Fwd-learning from Deps bitmaps with Backjump (Sect. 4.2), the
 // ASP-computation Decision and CompleteAssignment (Sect. 2), and a stability
-// check of total assignments.  In the batched form the workgroups are
-// persistent and take instances, largest first, from a queue.
+// check of total assignments.  In the batched form each workgroup solves one
+// instance; instances are launched by LDS size class, largest first.
 //
 // Data placement:
 //  * LDS: the assignment as 2 bits per variable (1 = true, 2 = false) and a
@@ -13,19 +13,19 @@
 //    buffers that spread a round's (literal, nogood) visits over the lanes.
 //  * HBM (read-only, per instance): nogood CSR, literal->nogood map CSR,
 //    rule table.  Visits read a map segment and then the nogood's literals.
-//  * HBM (per workgroup slot): levels, Deps bitmaps (W x 64 bit per
+//  * HBM (per instance slot): levels, Deps bitmaps (W x 64 bit per
 //    variable), the trail (assigned variables in order, whose tail is the
 //    round frontier), the lowest-id implier per variable, the learned
 //    nogoods and their literal occurrence lists.
 //
-// Control discipline: the search state (levels, queue pointers, counters,
+// Control discipline: the search state (decision level, trail pointers, counters,
 // status) is a struct that every lane of every wave holds and updates
 // identically; it is derived only from values that all lanes see alike (LDS
 // words read after a barrier, uniform global loads, block reductions), and
 // is pinned to scalar registers with readfirstlane.  No branch of the
 // control flow depends on the lane index, so the compiler cannot give lanes
 // different paths through the search loop, and single-writer effects are
-// value selects or identical stores from every lane.
+// identical stores from every lane.
 //
 // A round is a Jacobi step: every nogood reached from the previous round's
 // assignments is classified against the same assignment; among the nogoods
@@ -61,7 +61,6 @@ struct Ctl {
 struct Scr {
     unsigned long long conf_key;
     int32_t tail, clash, changed, pool_top, cap_err;
-    int32_t popq[kMaxWaves];
     int32_t flag[kMaxWaves];
     int32_t wsum[kMaxWaves + 1];
     unsigned long long red[kMaxWaves];
@@ -237,31 +236,8 @@ DEV unsigned long long alldec_word(int w, int cdl, int W) {
 }
 
 // --------------------------------------------------------- state moves
-DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst, uint8_t* slot) {
+DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     const InstDesc& d = a.inst[inst];
-    c.NO = a.ng_off + d.ng_off;
-    c.NL = a.ng_lits + d.ng_lits;
-    c.MO = a.map_off + d.map_off;
-    c.MI = a.map_ids + d.map_ids;
-    c.RH = a.rule_head + d.rules;
-    c.RO = a.rule_occ + d.rules;
-    c.RBO = a.rb_off + d.rb_off;
-    c.RBL = a.rb_lits + d.rb_lits;
-    c.ctrl = (SlotCtrl*)(slot + a.lay.ctrl);
-    c.val8 = (int8_t*)(slot + a.lay.val8);
-    c.lvl = (int32_t*)(slot + a.lay.lvl);
-    c.deps = (uint64_t*)(slot + a.lay.deps);
-    c.win = (int32_t*)(slot + a.lay.win);
-    c.trail = (int32_t*)(slot + a.lay.trail);
-    c.tlim = (int32_t*)(slot + a.lay.tlim);
-    c.dec = (int32_t*)(slot + a.lay.dec);
-    c.lptr = (int32_t*)(slot + a.lay.locc_ptr);
-    c.ln = (int32_t*)(slot + a.lay.locc_n);
-    c.lcap = (int32_t*)(slot + a.lay.locc_cap);
-    c.loff = (int32_t*)(slot + a.lay.l_off);
-    c.llits = (int32_t*)(slot + a.lay.l_lits);
-    c.pool = (int32_t*)(slot + a.lay.pool);
-    c.pool_cap = a.lay.pool_cap;
     k.inst = inst;
     k.A = uni(d.A);
     k.Rh = uni(d.Rh);
@@ -270,6 +246,31 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst, uint8_t* slot) 
     k.u0 = uni(d.u0);
     k.u1 = uni(d.u1);
     k.has_empty = uni(d.has_empty);
+    const SlotLayout lay = slot_layout(k.V, k.Rh, a.W, a.cap_ng, a.cap_lits);
+    uint8_t* slot = a.slots + a.slot_off[inst];
+    c.NO = a.ng_off + d.ng_off;
+    c.NL = a.ng_lits + d.ng_lits;
+    c.MO = a.map_off + d.map_off;
+    c.MI = a.map_ids + d.map_ids;
+    c.RH = a.rule_head + d.rules;
+    c.RO = a.rule_occ + d.rules;
+    c.RBO = a.rb_off + d.rb_off;
+    c.RBL = a.rb_lits + d.rb_lits;
+    c.ctrl = (SlotCtrl*)(slot + lay.ctrl);
+    c.val8 = (int8_t*)(slot + lay.val8);
+    c.lvl = (int32_t*)(slot + lay.lvl);
+    c.deps = (uint64_t*)(slot + lay.deps);
+    c.win = (int32_t*)(slot + lay.win);
+    c.trail = (int32_t*)(slot + lay.trail);
+    c.tlim = (int32_t*)(slot + lay.tlim);
+    c.dec = (int32_t*)(slot + lay.dec);
+    c.lptr = (int32_t*)(slot + lay.locc_ptr);
+    c.ln = (int32_t*)(slot + lay.locc_n);
+    c.lcap = (int32_t*)(slot + lay.locc_cap);
+    c.loff = (int32_t*)(slot + lay.l_off);
+    c.llits = (int32_t*)(slot + lay.l_lits);
+    c.pool = (int32_t*)(slot + lay.pool);
+    c.pool_cap = lay.pool_cap;
 }
 
 // Fresh search state: nothing assigned, no learned nogoods.
@@ -1004,29 +1005,18 @@ __global__ __launch_bounds__(MAXT) void k_search(KArgs a) {
     }
     const uint64_t t0 = wall_clock64();
     if (a.mode == MODE_SOLVE) {
-        uint8_t* slot = a.slots + (size_t)blockIdx.x * a.lay.stride;
-        for (;;) {
-            // one lane of the workgroup takes the next instance: every lane
-            // runs the atomic with an increment of 1 (lane 0 of wave 0) or 0
-            int q = atomicAdd(&a.queue[0], c.tid == 0 ? 1 : 0);
-            q = __shfl(q, 0, 64);
-            bar();
-            scr.popq[c.wid] = q;
-            bar();
-            q = uni(scr.popq[0]);
-            bar();
-            const int inst = q < a.n_inst ? uni(a.order[q]) : -1;
-            if (inst < 0) break;
-            bind_instance(c, k, a, inst, slot);
-            reset_search(c, k);
-            run_search(c, k, a, a.models + a.inst[inst].model, t0);
-            flush_counters(c, k);
-            write_result(c, k, a);
-            save_ctrl(c, k);
-        }
+        // one workgroup per instance; the hardware dispatcher keeps as many
+        // resident as LDS and wave slots allow
+        if ((int)blockIdx.x >= a.count) return;
+        const int inst = uni(a.order[a.first + (int)blockIdx.x]);
+        bind_instance(c, k, a, inst);
+        reset_search(c, k);
+        run_search(c, k, a, a.models + a.inst[inst].model, t0);
+        flush_counters(c, k);
+        write_result(c, k, a);
+        save_ctrl(c, k);
     } else {
-        uint8_t* slot = a.slots;
-        bind_instance(c, k, a, 0, slot);
+        bind_instance(c, k, a, 0);
         if (a.mode == MODE_STEPS) {
             load_ctrl(c, k);
             run_search(c, k, a, a.models + a.inst[0].model, t0);
@@ -1036,10 +1026,6 @@ __global__ __launch_bounds__(MAXT) void k_search(KArgs a) {
         flush_counters(c, k);
         save_ctrl(c, k);
     }
-}
-
-__global__ void k_reset_queue(int32_t* q) {
-    if (threadIdx.x < 2) q[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------------ launchers
@@ -1057,11 +1043,6 @@ hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipS
     case 1024: hipLaunchKernelGGL(k_search<1024>, dim3(grid), dim3(1024), lds, s, a); break;
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, q);
     return hipGetLastError();
 }
 

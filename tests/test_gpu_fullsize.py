@@ -21,13 +21,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 
-def _solve_batch(progs, budget, threads, wg_per_cu, cap_ng, cap_lits):
+def _solve_batch(progs, budget, threads, classes, cap_ng, cap_lits):
     import torch
     import paper_1909_01786_amd as P
     with ThreadPoolExecutor(16) as ex:
         gp = list(ex.map(lambda p: P.Program(p, learned_cap_ng=cap_ng,
                                              learned_cap_lits=cap_lits), progs))
-    b = P.Batch(gp, threads=threads, wg_per_cu=wg_per_cu).bind("cuda")
+    b = P.Batch(gp, threads=threads, classes=classes).bind("cuda")
     b.solve(P.limits(budget, 150000))
     torch.cuda.synchronize()
     return b.results()
@@ -58,7 +58,7 @@ def _sample_against_oracle(progs, verd, models, stats, budget, cap_ng, cap_lits,
 
 
 def test_random_batch_4096_bench_configuration():
-    """4096 uneven random programs, budget 2000, 128 threads x 4 per CU."""
+    """4096 uneven random programs, budget 2000, 128 threads, 4 LDS classes."""
     import bench
     t = time.time()
     progs = bench.make_batch(4096, 3000)

@@ -220,13 +220,14 @@ def test_api_errors(P):
 
 @pytest.mark.parametrize("threads", [64, 256])
 def test_batch_parity_mixed(P, threads):
-    """One persistent launch over programs of very different sizes."""
+    """One batched solve over programs of very different sizes (several LDS
+    classes, one workgroup each)."""
     progs = [aspgen.tiny_program(s, 4, 20) for s in range(40)]
     progs += [aspgen.single_random(1000 + s) for s in range(4)]
     progs += [aspgen.batch_hamiltonian(s) for s in range(4)]
     progs += [aspgen.batch_random(s, a_lo=100, a_hi=400) for s in range(8)]
     gp = [P.Program(p) for p in progs]
-    b = P.Batch(gp, threads=threads, wg_per_cu=2).bind("cuda")
+    b = P.Batch(gp, threads=threads, classes=3).bind("cuda")
     b.solve(P.limits(300, LIM_MS))
     verd, models, stats = b.results()
     for i, p in enumerate(progs):

@@ -42,6 +42,7 @@ __all__ = [
     "Program", "random_program", "tiny_program", "single_random", "batch_random",
     "coloring", "gnp_coloring", "hamiltonian", "random_digraph",
     "batch_hamiltonian", "from_rules", "save_program", "load_program",
+    "MPNN_F", "MPNN_H", "MPNN_L", "mpnn_weights", "decision_scores",
 ]
 
 
@@ -245,6 +246,44 @@ def batch_hamiltonian(i: int, batch_seed: int = 4000, n_lo: int = 60,
     n = int(rng.integers(n_lo, n_hi + 1))
     edges = random_digraph(rng, n, dmin, dmax)
     return hamiltonian(n, edges, 0, name=f"hc{batch_seed}_{i}")
+
+
+# ------------------------------------------------------- decision inputs
+MPNN_F, MPNN_H, MPNN_L = 8, 64, 3
+
+
+def mpnn_weights(seed: int, spread: int = 127) -> dict:
+    """Seeded integer weight codes for the atom-nogood scorer.
+
+    Matrices (shapes [in, out]) are integers in [-spread, spread], biases
+    integers in [-2^17, 2^17], the readout integers in [-127, 127] and its
+    bias in [-2^10, 2^10].
+    """
+    rng = _rng(6, seed)
+    F, H, L = MPNN_F, MPNN_H, MPNN_L
+
+    def mat(*shape):
+        return rng.integers(-spread, spread + 1, size=shape).astype(np.int64)
+
+    def bias(*shape):
+        return rng.integers(-(1 << 17), (1 << 17) + 1, size=shape).astype(np.int64)
+
+    w = {"Ev": mat(F, H), "Ec": mat(F, H)}
+    for k in ("P", "N", "S", "Q", "R", "T"):
+        w[k] = mat(L, H, H)
+    w["ev"], w["ec"] = bias(H), bias(H)
+    w["bc"], w["bv"] = bias(L, H), bias(L, H)
+    w["wo"] = rng.integers(-127, 128, size=H).astype(np.int64)
+    w["bo"] = int(rng.integers(-1024, 1025))
+    return w
+
+
+def decision_scores(seed: int, n_atoms: int, lo: int = -1000, hi: int = 1000) -> np.ndarray:
+    """Seeded integer per-atom decision scores (index 0 unused, kept 0)."""
+    rng = _rng(7, seed)
+    s = rng.integers(lo, hi + 1, size=n_atoms + 1).astype(np.int32)
+    s[0] = 0
+    return s
 
 
 # ------------------------------------------------------------------- files

@@ -93,7 +93,11 @@ def lib():
         L.or_model.argtypes = [P, np.ctypeslib.ndpointer(np.uint8, flags="C")]
         L.or_solve.argtypes = [C.c_int32, C.c_int32, i32p, i64p, i32p, C.c_int32, C.c_int32,
                                C.POINTER(Limits), np.ctypeslib.ndpointer(np.uint8, flags="C"),
-                               C.POINTER(Stats)]
+                               C.POINTER(Stats), C.c_void_p, C.c_int32]
+        L.or_set_scores.argtypes = [P, i32p, C.c_int32]
+        L.or_set_scores.restype = C.c_int32
+        L.or_score_mode.argtypes = [P, C.POINTER(C.c_int32)]
+        L.or_score_mode.restype = C.c_int32
         L.or_solve.restype = C.c_int32
         _lib = L
     return _lib
@@ -143,6 +147,21 @@ class Solver:
         if getattr(self, "_h", None):
             lib().or_free(self._h)
             self._h = None
+
+    def set_scores(self, score, fallback_after: int = 10) -> None:
+        """Drive Decision by per-atom integer scores (``score[p]`` for atom p,
+        index 0 unused) until ``fallback_after`` consecutive conflicts."""
+        sc = np.ascontiguousarray(score, np.int32)
+        if sc.shape != (int(self.dims()[1]) + 1,):
+            raise ValueError("score must have n_atoms + 1 entries")
+        if lib().or_set_scores(self._h, sc, int(fallback_after)) != 0:
+            raise ValueError("scores must be set before the first step")
+
+    def score_mode(self):
+        """(1 while the scores drive Decision else 0, current conflict run)."""
+        c = C.c_int32(0)
+        m = lib().or_score_mode(self._h, C.byref(c))
+        return int(m), int(c.value)
 
     def dims(self):
         d = np.zeros(16, np.int64)
@@ -199,14 +218,22 @@ class Solver:
                      off, lits, n0, int(d[10]), int(d[11]), int(d[12]), int(d[13]))
 
 
-def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = None):
-    """Encode and solve in one call; returns (status, model or None, stats)."""
+def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = None,
+          scores=None, fallback_after: int = 10):
+    """Encode and solve in one call; returns (status, model or None, stats).
+    ``scores`` (int32[n_atoms + 1]) selects the score-driven Decision."""
     L = lib()
     A = int(prog.n_atoms)
     m = np.zeros(max(A, 1), np.uint8)
     st = Stats()
+    sc = None
+    if scores is not None:
+        sc = np.ascontiguousarray(scores, np.int32)
+        if sc.shape != (A + 1,):
+            raise ValueError("scores must have n_atoms + 1 entries")
     rc = L.or_solve(A, int(prog.n_rules), np.ascontiguousarray(prog.head, np.int32),
                     np.ascontiguousarray(prog.body_off, np.int64),
                     np.ascontiguousarray(prog.body_lits, np.int32), int(W), int(gate),
-                    C.byref(limits) if limits else None, m, C.byref(st))
+                    C.byref(limits) if limits else None, m, C.byref(st),
+                    sc.ctypes.data if sc is not None else None, int(fallback_after))
     return rc, (m[:A].copy() if rc == SAT else None), st.as_dict()

@@ -22,8 +22,11 @@
  *               recent decision in the learned nogood.
  *   DECIDE   -- the ASP-computation Decision (Sect. 2): among rules r whose
  *               head is unassigned with T t_r in A and F n_r not in A, pick the
- *               highest occurrence count of the head (ties: lowest rule) and
- *               assign T b_r at a new level.
+ *               highest score of the head (ties: lowest rule) and assign T b_r
+ *               at a new level.  The score is the occurrence count of the
+ *               head in the static nogoods (the paper's occurrence heuristic)
+ *               or, when a per-atom integer score is supplied (the learned
+ *               Decision), that score until the fallback below fires.
  *   COMPLETE -- CompleteAssignment (Sect. 2): no applicable rule is left, so
  *               every unassigned original atom becomes false.
  *   GATE     -- on a total assignment, check M = least model of the reduct
@@ -40,7 +43,11 @@
  *     as Gelfond-Lifschitz, and the decided literal as T b_r (T n_r, not
  *     F n_r, then follows by propagation);
  *   - CompleteAssignment's falsifications take level cdl and the Deps of all
- *     decisions.
+ *     decisions;
+ *   - supplied scores fall back to the occurrence heuristic, for the rest of
+ *     the search, once `fallback_after` conflicts come in a row: the count
+ *     grows at every conflict and restarts from zero whenever a decision's
+ *     propagation ends at a conflict-free fixpoint.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -88,6 +95,11 @@ typedef struct {
     ivec ng_lits;
     ivec *map;                 /* [2(V+1)] literal -> nogood ids ascending */
     int32_t *occ;              /* [A+1] static occurrence count */
+    int32_t *score;            /* [A+1] supplied decision scores, or NULL */
+    int32_t use_score;         /* 1 while the supplied scores drive Decision */
+    int32_t fallback_after;    /* <0: never fall back */
+    int32_t consec;            /* conflicts since a decision reached a fixpoint */
+    int32_t dec_since_conf;    /* a decision was taken since the last conflict */
 
     /* assignment */
     int8_t *val;
@@ -353,7 +365,7 @@ void or_free(void *h) {
     free(s->ng_off.a); free(s->ng_lits.a);
     if (s->map)
         for (size_t i = 0; i < 2 * ((size_t)s->V + 1); ++i) free(s->map[i].a);
-    free(s->map); free(s->occ);
+    free(s->map); free(s->occ); free(s->score);
     free(s->val); free(s->lvl); free(s->deps); free(s->tmpdeps); free(s->pend_B);
     free(s->dec); free(s->frontier.a); free(s->win); free(s->winsign); free(s->touched);
     free(s->inM); free(s->inLM);
@@ -514,6 +526,14 @@ static void step_learn(or_solver *s, const or_limits *lim) {
         return;
     }
     s->st.conflicts += 1;
+    s->dec_since_conf = 0;
+    if (s->use_score) {
+        s->consec += 1;
+        if (s->fallback_after >= 0 && s->consec >= s->fallback_after) {
+            s->use_score = 0;
+            fnv(s, 7);
+        }
+    }
     /* levels(B), ascending: level l in 2..64W-1 for bit l-1, plus every
      * level 64W..cdl when the saturated bit 64W-1 is set */
     ivec lev = {0};
@@ -568,19 +588,29 @@ static void step_learn(or_solver *s, const or_limits *lim) {
 }
 
 /* S8: pick an applicable rule (T t_r in A, F n_r not in A, head unassigned)
- * by the highest occurrence count of its head, ties to the lowest rule. */
+ * by the highest score of its head, ties to the lowest rule. */
 static int32_t find_decision(const or_solver *s) {
-    int32_t best = -1, bestocc = -1;
+    const int32_t *sc = s->use_score ? s->score : s->occ;
+    int32_t best = -1;
+    int64_t bestkey = INT64_MIN;
     for (int32_t j = 0; j < s->Rh; ++j) {
         int32_t p = s->rhead[j], t = s->A + 3 * j + 2, n = s->A + 3 * j + 3;
         if (s->val[p] != 0 || s->val[t] != 1 || s->val[n] == -1) continue;
-        if (s->occ[p] > bestocc) { bestocc = s->occ[p]; best = j; }
+        if ((int64_t)sc[p] > bestkey) { bestkey = sc[p]; best = j; }
     }
     return best;
 }
 
+/* the search stands at a conflict-free fixpoint: if a decision led here,
+ * the run of consecutive conflicts is over */
+static void at_fixpoint(or_solver *s) {
+    if (s->dec_since_conf) s->consec = 0;
+}
+
 static void step_decide(or_solver *s, int32_t j) {
     const int32_t W = s->W;
+    at_fixpoint(s);
+    s->dec_since_conf = 1;
     int32_t b = s->A + 3 * j + 1;
     s->cdl += 1;
     s->dec[s->cdl] = b;
@@ -601,6 +631,7 @@ static void step_decide(or_solver *s, int32_t j) {
  * level cdl, depending on every decision made so far. */
 static void step_complete(or_solver *s) {
     const int32_t W = s->W;
+    at_fixpoint(s);
     s->frontier.n = 0;
     for (int32_t p = 1; p <= s->A; ++p) {
         if (s->val[p] != 0) continue;
@@ -624,6 +655,7 @@ static void step_complete(or_solver *s) {
  * model of the reduct (rules whose body- misses M, with body- deleted). */
 static void step_gate(or_solver *s) {
     const int32_t A = s->A, W = s->W;
+    at_fixpoint(s);
     for (int32_t p = 1; p <= A; ++p) { s->inM[p] = s->val[p] == 1; s->inLM[p] = 0; }
     for (int changed = 1; changed;) {
         changed = 0;
@@ -730,6 +762,30 @@ void or_nogoods(void *h, int32_t *off, int32_t *lits) {
     memcpy(lits, s->ng_lits.a, sizeof(int32_t) * (size_t)s->ng_lits.n);
 }
 
+/* Supply per-atom decision scores (score[p] for atom p = 1..A; score[0] is
+ * ignored) before the first step.  Returns 0, or OR_E_INVALID after the
+ * search has started. */
+int32_t or_set_scores(void *h, const int32_t *score, int32_t fallback_after) {
+    or_solver *s = (or_solver *)h;
+    if (s->last_step != ST_NONE || !score) return OR_E_INVALID;
+    if (!s->score) s->score = (int32_t *)calloc((size_t)s->A + 1, sizeof(int32_t));
+    memcpy(s->score, score, sizeof(int32_t) * ((size_t)s->A + 1));
+    s->score[0] = 0;
+    s->use_score = 1;
+    s->fallback_after = fallback_after;
+    s->consec = 0;
+    s->dec_since_conf = 0;
+    return 0;
+}
+
+/* 1 while the supplied scores drive Decision, 0 after the fallback (or when
+ * none were supplied); *consec gets the current run of conflicts */
+int32_t or_score_mode(void *h, int32_t *consec) {
+    or_solver *s = (or_solver *)h;
+    if (consec) *consec = s->consec;
+    return s->use_score;
+}
+
 void or_occ(void *h, int32_t *occ) {
     or_solver *s = (or_solver *)h;
     memcpy(occ, s->occ, sizeof(int32_t) * ((size_t)s->A + 1));
@@ -760,10 +816,11 @@ void or_model(void *h, uint8_t *model) {
 int32_t or_solve(int32_t n_atoms, int32_t n_rules, const int32_t *head,
                  const int64_t *body_off, const int32_t *body_lits, int32_t W,
                  int32_t gate_mode, const or_limits *lim, uint8_t *model,
-                 or_stats *st) {
+                 or_stats *st, const int32_t *score, int32_t fallback_after) {
     int32_t err = 0;
     void *h = or_create(n_atoms, n_rules, head, body_off, body_lits, W, gate_mode, &err);
     if (!h) return err;
+    if (score) or_set_scores(h, score, fallback_after);
     int32_t rc = or_run(h, lim, -1);
     if (model && rc == OR_SAT) or_model(h, model);
     if (st) or_get_stats(h, st);

@@ -68,6 +68,13 @@ extern "C" {
 #define ASP_GATE_UNFOUNDED 0  /* learn from the unfounded set's loop nogood */
 #define ASP_GATE_ALLDEC    1  /* learn the nogood of all current decisions */
 
+/* Decision heuristics (Sect. 2, the ASP-computation Decision: an applicable
+ * rule is chosen by a score of its head, ties to the lowest rule). */
+#define ASP_DECISION_OCC   0  /* occurrences of the head in Delta_0 */
+#define ASP_DECISION_SCORE 1  /* per-atom integer scores set on the device
+                                 (asp_set_scores, or the learned scorer of
+                                 asp_score_program / asp_score_batch) */
+
 typedef struct asp_program asp_program;
 typedef struct asp_batch asp_batch;
 
@@ -81,6 +88,13 @@ typedef struct {
     int64_t learned_cap_ng;    /* learned nogoods kept per instance; exceeding
                                   it ends the search with ASP_UNKNOWN */
     int64_t learned_cap_lits;  /* learned literals kept per instance; idem */
+    int32_t decision;          /* ASP_DECISION_OCC or ASP_DECISION_SCORE */
+    int32_t fallback_after;    /* ASP_DECISION_SCORE: after this many
+                                  conflicts in a row (the count restarts when a
+                                  decision's propagation ends at a
+                                  conflict-free fixpoint) the occurrence
+                                  heuristic takes over for the rest of the
+                                  search; < 0 never.  Default 10 */
 } asp_options;
 
 /* Run limits. */
@@ -143,6 +157,10 @@ typedef struct {
     int64_t learned_lits;
     int32_t initialised;          /* InitialPropagation has run */
     int32_t status;               /* ASP_RUNNING while the search is open */
+    int32_t score_mode;           /* 1 while per-atom scores drive Decision */
+    int32_t consec;               /* current run of conflicts (fallback count) */
+    int32_t dec_open;             /* a decision was taken since the last conflict */
+    int32_t reserved;
     int8_t *val;                  /* [n_vars+1] -1 / 0 / +1 */
     int32_t *lvl;                 /* [n_vars+1] decision level, 0 unassigned */
     uint64_t *deps;               /* [(n_vars+1)*W] Deps bitmaps */
@@ -161,7 +179,7 @@ typedef struct {
  *  body_off   : n_rules+1 offsets, non-decreasing, body_off[0] = 0
  *  body_lits  : +a (atom a) or -a (not a), 1 <= a <= n_atoms
  *  opt        : NULL = {W=1, gate=UNFOUNDED, learned_cap_ng=1<<20,
- *               learned_cap_lits=1<<22}
+ *               learned_cap_lits=1<<22, decision=OCC, fallback_after=10}
  * Repeated body literals are removed (first kept); a constraint holding both
  * a and not a is dropped.  Nogoods are generated per headed rule, then per
  * atom, then per constraint, and stably sorted by length (Sect. 4); their
@@ -206,6 +224,17 @@ int32_t asp_analyze_conflict(asp_program *prog, void *stream,
                              const asp_limits *lim, int32_t *learned_lits,
                              int32_t cap, int32_t *learned_len,
                              int32_t *backjump_level);
+
+/* Set the decision scores of a bound program: scores[p] for atom p =
+ * 1..n_atoms (scores[0] ignored), any int32 values, copied from the host on
+ * `stream`; the score of each rule's head is then gathered on the device.
+ * Programs loaded with ASP_DECISION_SCORE must have scores set (here or by
+ * asp_score_program) after every asp_bind_device and before searching, or
+ * the search calls return ASP_E_STATE.  Synchronous. */
+int32_t asp_set_scores(asp_program *prog, const int32_t *scores, void *stream);
+
+/* Copy the program's current device scores (n_atoms+1 int32) to the host. */
+int32_t asp_get_scores(asp_program *prog, int32_t *scores, void *stream);
 
 /* Run the next n_steps search steps of any kind (n_steps < 0: to the end).
  * Returns the search status (ASP_RUNNING if still open); *stats optional. */
@@ -260,6 +289,80 @@ int32_t asp_batch_results(asp_batch *batch, void *stream, int32_t *verdicts,
 int32_t asp_batch_last_ms(asp_batch *batch, double *ms);
 
 int32_t asp_batch_free(asp_batch *batch);
+
+/* Scores of a batch instance i (see asp_set_scores / asp_get_scores). */
+int32_t asp_batch_set_scores(asp_batch *batch, int32_t i, const int32_t *scores,
+                             void *stream);
+int32_t asp_batch_get_scores(asp_batch *batch, int32_t i, int32_t *scores,
+                             void *stream);
+
+/* ------------------------------------------------- learned Decision scorer
+ * A message-passing network over the bipartite graph of variables and the
+ * static nogoods Delta_0 (edges: the nogood literals, with their sign) gives
+ * each atom an integer score for the score-driven Decision.  It is
+ * quantisation-aware: matrices hold integer codes in [-127, 127] stored as
+ * bfloat16 and activations are integer codes in [0, 255], so every 64-term
+ * product on the matrix cores (bfloat16 operands, float32 accumulation) is
+ * an exact integer below 2^21 and the scores do not depend on the order of
+ * any sum.  With act(z) = 0 for z <= 0, else min(255, (z + 256) >> 9), and
+ * norm(s, n) = s >> k rounded half up, k = ceil(log2 n) (k = 0 for n <= 1):
+ *   embed   hv = act(x Ev + ev),  hc = act(y Ec + ec)
+ *   layer l hc = act(hc S_l + norm(sum_{Tv in c} hv P_l + sum_{Fv in c} hv N_l, |c|) + bc_l)
+ *           hv = act(hv T_l + norm(sum_{c with Tv} hc Q_l + sum_{c with Fv} hc R_l, deg v) + bv_l)
+ *   score   s_v = hv wo + bo    (atoms v = 1..n_atoms)
+ * Features, 32 standing for 1 and r(a, b) = (a + b/2) / b in integers:
+ *   x_v = [32, 32*atom, 32*is_b, 32*is_t, 32*is_n, r(32, 1 + #c with Tv),
+ *          r(32, 1 + #c with Fv), 0]
+ *   y_c = [32, r(32, |c|), 32*(|c|=1), 32*(|c|=2), 32*(|c|=3), 32*(|c|>=4),
+ *          r(32 * #positive literals, |c|), 0]
+ * Matrices are [in][out], row-major, bfloat16 bit patterns. */
+#define ASP_SCORER_F 8
+#define ASP_SCORER_H 64
+#define ASP_SCORER_L 3
+
+typedef struct {
+    uint16_t Ev[ASP_SCORER_F * ASP_SCORER_H], Ec[ASP_SCORER_F * ASP_SCORER_H];
+    uint16_t P[ASP_SCORER_L * ASP_SCORER_H * ASP_SCORER_H];
+    uint16_t N[ASP_SCORER_L * ASP_SCORER_H * ASP_SCORER_H];
+    uint16_t S[ASP_SCORER_L * ASP_SCORER_H * ASP_SCORER_H];
+    uint16_t Q[ASP_SCORER_L * ASP_SCORER_H * ASP_SCORER_H];
+    uint16_t R[ASP_SCORER_L * ASP_SCORER_H * ASP_SCORER_H];
+    uint16_t T[ASP_SCORER_L * ASP_SCORER_H * ASP_SCORER_H];
+    int32_t ev[ASP_SCORER_H], ec[ASP_SCORER_H];
+    int32_t bc[ASP_SCORER_L * ASP_SCORER_H], bv[ASP_SCORER_L * ASP_SCORER_H];
+    int32_t wo[ASP_SCORER_H];   /* in [-127, 127] */
+    int32_t bo;
+    int32_t reserved[63];
+} asp_scorer_weights;
+
+/* Device workspace (bytes) the scorer needs for the bound program / batch. */
+int32_t asp_scorer_workspace(const asp_program *prog, uint64_t *bytes);
+int32_t asp_batch_scorer_workspace(const asp_batch *batch, uint64_t *bytes);
+
+/* Score every atom with the network (weights: host copy, validated: matrix
+ * entries must be integers in [-127, 127], biases within +-2^24) into the
+ * device scores used by ASP_DECISION_SCORE.  ws: device memory of at least
+ * the workspace size, 256-byte aligned.  asp_score_program is synchronous;
+ * asp_score_batch enqueues on `stream` (all instances in one set of
+ * launches).  Errors: ASP_E_INVALID (weights), ASP_E_CAPACITY (workspace). */
+int32_t asp_score_program(asp_program *prog, const asp_scorer_weights *w, void *ws,
+                          uint64_t ws_bytes, void *stream);
+int32_t asp_score_batch(asp_batch *batch, const asp_scorer_weights *w, void *ws,
+                        uint64_t ws_bytes, void *stream);
+
+/* Train the scorer's readout on the device (the learned Decision's
+ * training): with the matrices of w fixed, the scorer runs once over the
+ * batch, then `steps` full-batch Adam steps (learning rate lr) minimise the
+ * mean binary cross-entropy of sigmoid(sum_j (hv_j / 256) wb[j] + wb[64])
+ * against labels, where hv is an atom's code vector after the last layer.
+ * labels: host int8, laid out like the models output (n_atoms per instance,
+ * in batch order): 1 = true in the answer set found by the plain search,
+ * 0 = false, -1 = no label.  wb_out[65] (host) holds the starting weights on
+ * entry and the trained ones on return; loss_out[steps] (optional) the mean
+ * loss before each step.  steps in 1..4096.  Synchronous. */
+int32_t asp_batch_train_readout(asp_batch *batch, const asp_scorer_weights *w, void *ws,
+                                uint64_t ws_bytes, const int8_t *labels, int32_t steps,
+                                float lr, float *wb_out, float *loss_out, void *stream);
 
 /* ------------------------------------------------------------- misc */
 const char *asp_status_str(int32_t status);

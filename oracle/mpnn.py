@@ -26,7 +26,7 @@ Features (codes, 32 standing for 1): x_v = [32, 32 if v is an atom, 32 if
 v is some b_r, t_r, n_r (three entries), r(32, 1 + #nogoods with Tv),
 r(32, 1 + #nogoods with Fv), 0]; y_c = [32, r(32, |c|), 32 if |c| = 1, 2, 3,
 >= 4 (four entries), r(32 #positive literals, |c|), 0], where
-r(a, b) = (a + b // 2) // b is a / b rounded half up.
+r(a, b) = (a + b // 2) // b is a / b rounded half up (0 when b = 0).
 """
 from __future__ import annotations
 
@@ -63,10 +63,11 @@ def graph_of(prog) -> Graph:
 
 
 def rdiv(a, b):
-    """a / b rounded half up, for a >= 0 and b >= 1 (integers)."""
+    """a / b rounded half up, for a >= 0 and b >= 1 (integers); 0 where b = 0
+    (the empty nogood of an empty-body constraint)."""
     a = np.asarray(a, np.int64)
     b = np.asarray(b, np.int64)
-    return (a + b // 2) // b
+    return np.where(b > 0, (a + b // 2) // np.maximum(b, 1), 0)
 
 
 def act(z):

@@ -5,4 +5,5 @@ ASP-solving", as hand-written HIP behind a C ABI (include/asp.h).
 ``binding`` marshals arguments to the library; ``build`` compiles it.
 """
 from .binding import (Batch, Program, AspError, limits, options, lib,  # noqa: F401
-                      SAT, UNSAT, UNKNOWN, FIXPOINT, CONFLICT, RUNNING)
+                      scorer_weights, SAT, UNSAT, UNKNOWN, FIXPOINT, CONFLICT, RUNNING,
+                      DECISION_OCC, DECISION_SCORE)

@@ -19,6 +19,8 @@ OK, SAT, UNSAT, UNKNOWN, FIXPOINT, CONFLICT, RUNNING = 0, 1, 2, 3, 4, 5, 6
 E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_INTERNAL, E_TIMEOUT = -1, -2, -3, -4, -5, -6
 STEP_NONE, STEP_INIT, STEP_ROUND, STEP_LEARN, STEP_DECIDE, STEP_COMPLETE, STEP_GATE, STEP_DONE = range(8)
 GATE_UNFOUNDED, GATE_ALLDEC = 0, 1
+DECISION_OCC, DECISION_SCORE = 0, 1
+SCORER_F, SCORER_H, SCORER_L = 8, 64, 3
 
 
 class AspError(RuntimeError):
@@ -29,7 +31,8 @@ class AspError(RuntimeError):
 
 class asp_options(C.Structure):
     _fields_ = [("W", C.c_int32), ("gate", C.c_int32), ("learned_cap_ng", C.c_int64),
-                ("learned_cap_lits", C.c_int64)]
+                ("learned_cap_lits", C.c_int64), ("decision", C.c_int32),
+                ("fallback_after", C.c_int32)]
 
 
 class asp_limits(C.Structure):
@@ -67,9 +70,54 @@ class asp_state(C.Structure):
     _fields_ = [("n_vars", C.c_int32), ("W", C.c_int32), ("cdl", C.c_int32),
                 ("frontier_len", C.c_int32), ("n_learned", C.c_int32), ("pending", C.c_int32),
                 ("learned_lits", C.c_int64), ("initialised", C.c_int32), ("status", C.c_int32),
-                ("val", C.c_void_p), ("lvl", C.c_void_p), ("deps", C.c_void_p),
+                ("score_mode", C.c_int32), ("consec", C.c_int32), ("dec_open", C.c_int32),
+                ("reserved", C.c_int32), ("val", C.c_void_p), ("lvl", C.c_void_p), ("deps", C.c_void_p),
                 ("dec", C.c_void_p), ("frontier", C.c_void_p), ("learned_off", C.c_void_p),
                 ("learned", C.c_void_p), ("stats", asp_stats)]
+
+
+_HH = SCORER_L * SCORER_H * SCORER_H
+_FH = SCORER_F * SCORER_H
+_LH = SCORER_L * SCORER_H
+
+
+class asp_scorer_weights(C.Structure):
+    _fields_ = [("Ev", C.c_uint16 * _FH), ("Ec", C.c_uint16 * _FH)] + \
+        [(k, C.c_uint16 * _HH) for k in ("P", "N", "S", "Q", "R", "T")] + \
+        [("ev", C.c_int32 * SCORER_H), ("ec", C.c_int32 * SCORER_H), ("bc", C.c_int32 * _LH),
+         ("bv", C.c_int32 * _LH), ("wo", C.c_int32 * SCORER_H), ("bo", C.c_int32),
+         ("reserved", C.c_int32 * 63)]
+
+
+def _bf16_bits(codes) -> np.ndarray:
+    """Integer codes (|k| <= 127, exact in bfloat16) as bfloat16 bit patterns."""
+    f = np.ascontiguousarray(np.asarray(codes, np.float32).reshape(-1))
+    return (f.view(np.uint32) >> 16).astype(np.uint16)
+
+
+WEIGHTS_PATH = os.path.join(HERE, "weights", "scorer.npz")
+
+
+def load_weights(path: str = WEIGHTS_PATH) -> dict:
+    """Integer weight codes of the scorer, as written by train_scorer.py."""
+    z = np.load(path, allow_pickle=False)
+    keys = ("Ev", "Ec", "P", "N", "S", "Q", "R", "T", "ev", "ec", "bc", "bv", "wo")
+    w = {k: z[k].astype(np.int64) for k in keys}
+    w["bo"] = int(z["bo"])
+    return w
+
+
+def scorer_weights(w: dict) -> asp_scorer_weights:
+    """Pack a dict of integer weight codes ([in, out] matrices; see asp.h)."""
+    out = asp_scorer_weights()
+    for k in ("Ev", "Ec", "P", "N", "S", "Q", "R", "T"):
+        bits = _bf16_bits(w[k])
+        C.memmove(getattr(out, k), bits.ctypes.data, bits.nbytes)
+    for k in ("ev", "ec", "bc", "bv", "wo"):
+        v = np.ascontiguousarray(np.asarray(w[k], np.int64).reshape(-1).astype(np.int32))
+        C.memmove(getattr(out, k), v.ctypes.data, v.nbytes)
+    out.bo = int(w["bo"])
+    return out
 
 
 EXPORTS = (
@@ -77,7 +125,10 @@ EXPORTS = (
     "asp_propagate", "asp_analyze_conflict", "asp_run_steps", "asp_solve",
     "asp_state_export", "asp_state_import", "asp_batch_create", "asp_batch_bind",
     "asp_solve_batch", "asp_batch_results", "asp_batch_last_ms", "asp_batch_free",
-    "asp_status_str", "asp_last_error",
+    "asp_status_str", "asp_last_error", "asp_set_scores", "asp_get_scores",
+    "asp_batch_set_scores", "asp_batch_get_scores", "asp_scorer_workspace",
+    "asp_batch_scorer_workspace", "asp_score_program", "asp_score_batch",
+    "asp_batch_train_readout",
 )
 
 _lib = None
@@ -113,6 +164,16 @@ def lib():
             "asp_batch_free": (i32, [P]),
             "asp_status_str": (C.c_char_p, [i32]),
             "asp_last_error": (i32, [C.c_char_p, u64]),
+            "asp_set_scores": (i32, [P, P, P]),
+            "asp_get_scores": (i32, [P, P, P]),
+            "asp_batch_set_scores": (i32, [P, i32, P, P]),
+            "asp_batch_get_scores": (i32, [P, i32, P, P]),
+            "asp_scorer_workspace": (i32, [P, C.POINTER(u64)]),
+            "asp_batch_scorer_workspace": (i32, [P, C.POINTER(u64)]),
+            "asp_score_program": (i32, [P, C.POINTER(asp_scorer_weights), P, u64, P]),
+            "asp_score_batch": (i32, [P, C.POINTER(asp_scorer_weights), P, u64, P]),
+            "asp_batch_train_readout": (i32, [P, C.POINTER(asp_scorer_weights), P, u64, P, i32,
+                                              C.c_float, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -158,8 +219,10 @@ def limits(max_conflicts: int = -1, max_ms: int = 0) -> asp_limits:
 
 
 def options(W: int = 1, gate: int = GATE_UNFOUNDED, learned_cap_ng: int = 1 << 20,
-            learned_cap_lits: int = 1 << 22) -> asp_options:
-    return asp_options(int(W), int(gate), int(learned_cap_ng), int(learned_cap_lits))
+            learned_cap_lits: int = 1 << 22, decision: int = DECISION_OCC,
+            fallback_after: int = 10) -> asp_options:
+    return asp_options(int(W), int(gate), int(learned_cap_ng), int(learned_cap_lits),
+                       int(decision), int(fallback_after))
 
 
 @dataclass
@@ -178,17 +241,21 @@ class State:
     initialised: int
     status: int
     stats: dict
+    score_mode: int = 0
+    consec: int = 0
+    dec_open: int = 0
 
 
 class Program:
     """A ground program encoded by libasp (asp_load_program)."""
 
     def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED,
-                 learned_cap_ng: int = 1 << 20, learned_cap_lits: int = 1 << 22):
+                 learned_cap_ng: int = 1 << 20, learned_cap_lits: int = 1 << 22,
+                 decision: int = DECISION_OCC, fallback_after: int = 10):
         self._head = np.ascontiguousarray(prog.head, np.int32)
         self._off = np.ascontiguousarray(prog.body_off, np.int64)
         self._lits = np.ascontiguousarray(prog.body_lits, np.int32)
-        self.opt = options(W, gate, learned_cap_ng, learned_cap_lits)
+        self.opt = options(W, gate, learned_cap_ng, learned_cap_lits, decision, fallback_after)
         self.sizes = asp_sizes()
         h = C.c_void_p()
         _check(lib().asp_load_program(int(prog.n_atoms), int(self._head.shape[0]),
@@ -225,6 +292,28 @@ class Program:
         _check(lib().asp_bind_device(self._h, C.c_void_p(self.arena.data_ptr()),
                                      int(self.arena.numel()), _stream_ptr(stream), C.byref(sch)))
         return self
+
+    def set_scores(self, scores):
+        """Decision scores of atoms 0..n_atoms (index 0 ignored)."""
+        sc = np.ascontiguousarray(scores, np.int32)
+        if sc.shape != (self.n_atoms + 1,):
+            raise ValueError("scores must have n_atoms + 1 entries")
+        _check(lib().asp_set_scores(self._h, _ptr(sc), _stream_ptr(self.stream)))
+
+    def get_scores(self) -> np.ndarray:
+        out = np.zeros(self.n_atoms + 1, np.int32)
+        _check(lib().asp_get_scores(self._h, _ptr(out), _stream_ptr(self.stream)))
+        return out
+
+    def score(self, weights: dict, device="cuda"):
+        """Run the learned scorer on the device; returns the atom scores."""
+        nb = C.c_uint64(0)
+        _check(lib().asp_scorer_workspace(self._h, C.byref(nb)))
+        ws = _arena(nb.value, device)
+        w = scorer_weights(weights)
+        _check(lib().asp_score_program(self._h, C.byref(w), C.c_void_p(ws.data_ptr()),
+                                       int(ws.numel()), _stream_ptr(self.stream)))
+        return self.get_scores()
 
     def propagate(self, max_rounds: int = 0):
         r = asp_prop_result()
@@ -269,7 +358,8 @@ class Program:
         _check(lib().asp_state_export(self._h, _stream_ptr(self.stream), C.byref(st)))
         return State(V, W, st.cdl, val, lvl, deps.reshape(V + 1, W), dec,
                      fr[:st.frontier_len], loff, lits[:st.learned_lits], st.pending,
-                     st.initialised, st.status, st.stats.as_dict())
+                     st.initialised, st.status, st.stats.as_dict(), st.score_mode, st.consec,
+                     st.dec_open)
 
     def import_state(self, s: State):
         st = asp_state()
@@ -287,6 +377,7 @@ class Program:
         st.learned_lits = int(lits.shape[0])
         st.initialised = int(s.initialised)
         st.status = RUNNING
+        st.score_mode, st.consec, st.dec_open = int(s.score_mode), int(s.consec), int(s.dec_open)
         st.val, st.lvl, st.deps, st.dec = _ptr(val), _ptr(lvl), _ptr(deps), _ptr(dec)
         st.frontier, st.learned_off, st.learned = _ptr(fr), _ptr(loff), _ptr(lits)
         for k, v in (s.stats or {}).items():
@@ -326,6 +417,50 @@ class Batch:
         _check(lib().asp_batch_bind(self._h, C.c_void_p(self.arena.data_ptr()),
                                     int(self.arena.numel()), _stream_ptr(stream)))
         return self
+
+    def set_scores(self, i: int, scores):
+        sc = np.ascontiguousarray(scores, np.int32)
+        if sc.shape != (self.programs[i].n_atoms + 1,):
+            raise ValueError("scores must have n_atoms + 1 entries")
+        _check(lib().asp_batch_set_scores(self._h, int(i), _ptr(sc), _stream_ptr(self.stream)))
+
+    def get_scores(self, i: int) -> np.ndarray:
+        out = np.zeros(self.programs[i].n_atoms + 1, np.int32)
+        _check(lib().asp_batch_get_scores(self._h, int(i), _ptr(out), _stream_ptr(self.stream)))
+        return out
+
+    def scorer_workspace(self, device="cuda"):
+        nb = C.c_uint64(0)
+        _check(lib().asp_batch_scorer_workspace(self._h, C.byref(nb)))
+        return _arena(nb.value, device)
+
+    def score(self, weights, ws=None):
+        """Enqueue the learned scorer over every instance (asynchronous).
+        ``weights``: a dict of codes or a packed asp_scorer_weights."""
+        if ws is None:
+            if getattr(self, "_ws", None) is None:
+                self._ws = self.scorer_workspace(self.arena.device)
+            ws = self._ws
+        w = weights if isinstance(weights, asp_scorer_weights) else scorer_weights(weights)
+        self._w = w
+        _check(lib().asp_score_batch(self._h, C.byref(w), C.c_void_p(ws.data_ptr()),
+                                     int(ws.numel()), _stream_ptr(self.stream)))
+
+    def train_readout(self, weights, labels, steps: int = 400, lr: float = 0.05, wb0=None):
+        """Train the scorer readout on the device; returns (wb[65], losses)."""
+        if getattr(self, "_ws", None) is None:
+            self._ws = self.scorer_workspace(self.arena.device)
+        w = weights if isinstance(weights, asp_scorer_weights) else scorer_weights(weights)
+        lab = np.ascontiguousarray(labels, np.int8)
+        if lab.shape != (self.model_bytes,):
+            raise ValueError("labels must have one entry per atom of the batch")
+        wb = np.zeros(65, np.float32) if wb0 is None else np.ascontiguousarray(wb0, np.float32)
+        loss = np.zeros(int(steps), np.float32)
+        _check(lib().asp_batch_train_readout(self._h, C.byref(w), C.c_void_p(self._ws.data_ptr()),
+                                             int(self._ws.numel()), _ptr(lab), int(steps),
+                                             float(lr), _ptr(wb), _ptr(loss),
+                                             _stream_ptr(self.stream)))
+        return wb, loss
 
     def solve(self, lim: asp_limits | None = None):
         """Enqueue the batched solve on the stream (asynchronous)."""

@@ -1,7 +1,8 @@
 """Build libasp.so (HIP for gfx950) in-tree with hipcc.
 
 The library is the product path: ``csrc/encode.cpp`` (host encoding),
-``csrc/solver.hip`` (device search) and ``csrc/api.cpp`` (C ABI of
+``csrc/solver.hip`` (device search), ``csrc/scorer.hip`` (learned Decision
+scorer) and ``csrc/api.cpp`` (C ABI of
 ``include/asp.h``).  Packed FP32 instructions are disabled for every HIP
 translation unit.
 """
@@ -15,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libasp.so")
-SOURCES = ["encode.cpp", "api.cpp", "solver.hip"]
+SOURCES = ["encode.cpp", "api.cpp", "solver.hip", "scorer.hip"]
 HEADERS = ["encode.h", "layout.h"]
 ARCH = os.environ.get("ASP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

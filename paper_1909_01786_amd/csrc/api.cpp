@@ -18,6 +18,7 @@
 #include "../../include/asp.h"
 #include "encode.h"
 #include "layout.h"
+#include "scorer.h"
 
 namespace asp {
 size_t lds_bytes(int threads, int words);
@@ -81,17 +82,17 @@ struct LaunchClass {
 };
 
 struct Plan {
-    int32_t n = 0, threads = 256, W = 1, gate = 0;
+    int32_t n = 0, threads = 256, W = 1, gate = 0, decision = 0, fallback_after = 10;
     int64_t Vmax = 0, Rhmax = 0, cap_ng = 0, cap_lits = 0;
     std::vector<LaunchClass> classes;
     std::vector<InstDesc> desc;
     std::vector<int32_t> order;
     std::vector<int64_t> slot_off;      // per instance, bytes from off_slots
     uint64_t off_desc = 0, off_order = 0, off_slotoff = 0, off_ngo = 0, off_ngl = 0, off_mo = 0,
-             off_mi = 0, off_rh = 0, off_ro = 0, off_rbo = 0, off_rbl = 0, off_verd = 0,
-             off_stats = 0, off_models = 0, off_slots = 0, total = 0;
+             off_mi = 0, off_rh = 0, off_ro = 0, off_rbo = 0, off_rbl = 0, off_asc = 0,
+             off_rs = 0, off_verd = 0, off_stats = 0, off_models = 0, off_slots = 0, total = 0;
     int64_t tot_ngo = 0, tot_ngl = 0, tot_mo = 0, tot_mi = 0, tot_rules = 0, tot_rbo = 0,
-            tot_rbl = 0, tot_model = 0, slots_bytes = 0;
+            tot_rbl = 0, tot_model = 0, tot_asc = 0, slots_bytes = 0;
     size_t max_lds() const {
         size_t m = 0;
         for (auto& c : classes) m = std::max(m, c.lds);
@@ -99,15 +100,30 @@ struct Plan {
     }
 };
 
+// Scorer workspace: weights, per-instance row offsets, tile lists, and the
+// activation codes (64 bytes per variable and per static nogood).
+struct ScorerPlan {
+    std::vector<int64_t> hv_off, hc_off;
+    std::vector<ScorerTile> vt, ct;
+    std::vector<int32_t> list;
+    uint64_t off_w = 0, off_hvo = 0, off_hco = 0, off_vt = 0, off_ct = 0, off_list = 0,
+             off_lab = 0, off_train = 0, total = 0;
+    bool planned = false;
+    uint8_t* uploaded_to = nullptr;   // workspace holding the tables
+    asp_scorer_weights w{};           // host copy kept alive for async copies
+};
+
 struct asp_program {
     HostProgram hp;
     asp_options opt{};
     // single-instance binding
     bool bound = false;
+    bool scores_ready = false;
     uint8_t* arena = nullptr;
     uint64_t bytes = 0;
     Plan plan;
     int32_t threads = 256;
+    ScorerPlan scorer;
 };
 
 struct asp_batch {
@@ -115,6 +131,9 @@ struct asp_batch {
     asp_options opt{};
     Plan plan;
     bool bound = false;
+    std::vector<uint8_t> ready;       // decision scores set, per instance
+    int32_t n_ready = 0;
+    ScorerPlan scorer;
     uint8_t* arena = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_fork = nullptr;
     std::vector<hipStream_t> streams;    // one per launch class (default priority)
@@ -126,6 +145,8 @@ namespace {
 
 // Wall-clock guard applied when the caller gives none: every launch ends.
 constexpr int64_t kDefaultMaxMs = 600000;
+// Readout training steps per call.
+constexpr int32_t kMaxTrainSteps = 4096;
 
 asp_options default_options() {
     asp_options o;
@@ -133,6 +154,8 @@ asp_options default_options() {
     o.gate = ASP_GATE_UNFOUNDED;
     o.learned_cap_ng = 1 << 20;
     o.learned_cap_lits = 1 << 22;
+    o.decision = ASP_DECISION_OCC;
+    o.fallback_after = 10;
     return o;
 }
 
@@ -153,6 +176,8 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.threads = threads;
     P.W = opt.W;
     P.gate = opt.gate;
+    P.decision = opt.decision;
+    P.fallback_after = opt.fallback_after;
     P.cap_ng = opt.learned_cap_ng;
     P.cap_lits = opt.learned_cap_lits;
     P.desc.resize(P.n);
@@ -168,6 +193,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
         d.rb_off = P.tot_rbo;
         d.rb_lits = P.tot_rbl;
         d.model = P.tot_model;
+        d.ascore = P.tot_asc;
         d.A = h.A;
         d.Rh = h.Rh;
         d.V = h.V;
@@ -186,6 +212,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
         P.tot_rbo += (int64_t)h.rb_off.size();
         P.tot_rbl += (int64_t)h.rb_lits.size();
         P.tot_model += h.A;
+        P.tot_asc += (int64_t)h.A + 1;
         P.Vmax = std::max<int64_t>(P.Vmax, h.V);
         P.Rhmax = std::max<int64_t>(P.Rhmax, h.Rh);
         P.slot_off[i] = P.slots_bytes;
@@ -234,6 +261,8 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.off_ro = take(4 * (uint64_t)P.tot_rules);
     P.off_rbo = take(4 * (uint64_t)P.tot_rbo);
     P.off_rbl = take(4 * (uint64_t)P.tot_rbl);
+    P.off_asc = take(4 * (uint64_t)P.tot_asc);
+    P.off_rs = take(4 * (uint64_t)P.tot_rules);
     P.off_verd = take(4 * (uint64_t)P.n);
     P.off_stats = take(sizeof(DevStats) * (uint64_t)P.n);
     P.off_models = take((uint64_t)P.tot_model + 1);
@@ -295,6 +324,7 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& 
     a.map_ids = (const int32_t*)(arena + P.off_mi);
     a.rule_head = (const int32_t*)(arena + P.off_rh);
     a.rule_occ = (const int32_t*)(arena + P.off_ro);
+    a.rule_score = (const int32_t*)(arena + P.off_rs);
     a.rb_off = (const int32_t*)(arena + P.off_rbo);
     a.rb_lits = (const int32_t*)(arena + P.off_rbl);
     a.slots = arena + P.off_slots;
@@ -304,6 +334,8 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& 
     a.models = arena + P.off_models;
     a.W = P.W;
     a.gate_mode = P.gate;
+    a.decision = P.decision;
+    a.fallback_after = P.fallback_after;
     a.words = lc.words;
     a.step_mask = 0;
     a.max_steps = -1;
@@ -401,6 +433,171 @@ T* slot_arr(asp_program* p, int64_t off) {
     return (T*)(p->arena + p->plan.off_slots + off);
 }
 
+// ------------------------------------------------------ decision scores
+// Upload atom scores of instance i and gather its rule scores on the device.
+int32_t put_scores(const Plan& P, uint8_t* arena, int32_t i, const int32_t* scores, hipStream_t s) {
+    const InstDesc& d = P.desc[i];
+    std::vector<int32_t> sc(scores, scores + d.A + 1);
+    sc[0] = 0;
+    HIPCHK(hipMemcpyAsync(arena + P.off_asc + 4 * (uint64_t)d.ascore, sc.data(), 4 * sc.size(),
+                          hipMemcpyHostToDevice, s));
+    ScorerArgs a{};
+    a.inst = (const InstDesc*)(arena + P.off_desc);
+    a.rule_head = (const int32_t*)(arena + P.off_rh);
+    a.atom_score = (int32_t*)(arena + P.off_asc);
+    a.rule_score = (int32_t*)(arena + P.off_rs);
+    a.inst_list = nullptr;   // gather instance i only
+    a.single = i;
+    HIPCHK(launch_rule_scores(a, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ASP_OK;
+}
+
+int32_t get_scores(const Plan& P, uint8_t* arena, int32_t i, int32_t* out, hipStream_t s) {
+    const InstDesc& d = P.desc[i];
+    HIPCHK(hipMemcpyAsync(out, arena + P.off_asc + 4 * (uint64_t)d.ascore, 4 * ((size_t)d.A + 1),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ASP_OK;
+}
+
+// ------------------------------------------------------------- scorer
+bool bf16_code(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f == (float)(int)f && f >= -127.f && f <= 127.f;
+}
+
+int32_t check_weights(const asp_scorer_weights* w) {
+    if (!w) return fail(ASP_E_INVALID, "null scorer weights");
+    auto mats = [&](const uint16_t* m, size_t n) {
+        for (size_t i = 0; i < n; ++i)
+            if (!bf16_code(m[i])) return false;
+        return true;
+    };
+    const size_t HH = (size_t)ASP_SCORER_L * ASP_SCORER_H * ASP_SCORER_H;
+    const size_t FH = (size_t)ASP_SCORER_F * ASP_SCORER_H;
+    if (!mats(w->Ev, FH) || !mats(w->Ec, FH) || !mats(w->P, HH) || !mats(w->N, HH) ||
+        !mats(w->S, HH) || !mats(w->Q, HH) || !mats(w->R, HH) || !mats(w->T, HH))
+        return fail(ASP_E_INVALID, "scorer matrices must hold integers in [-127, 127]");
+    const int32_t lim = 1 << 24;
+    auto vecs = [&](const int32_t* v, size_t n, int32_t m) {
+        for (size_t i = 0; i < n; ++i)
+            if (v[i] < -m || v[i] > m) return false;
+        return true;
+    };
+    const size_t LH = (size_t)ASP_SCORER_L * ASP_SCORER_H;
+    if (!vecs(w->ev, ASP_SCORER_H, lim) || !vecs(w->ec, ASP_SCORER_H, lim) ||
+        !vecs(w->bc, LH, lim) || !vecs(w->bv, LH, lim) || !vecs(&w->bo, 1, lim))
+        return fail(ASP_E_INVALID, "scorer biases must be within +-2^24");
+    if (!vecs(w->wo, ASP_SCORER_H, 127)) return fail(ASP_E_INVALID, "scorer readout must be in [-127, 127]");
+    return ASP_OK;
+}
+
+void scorer_plan(const std::vector<const HostProgram*>& progs, ScorerPlan& S) {
+    if (S.planned) return;
+    const size_t n = progs.size();
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    S.hv_off.assign(n, 0);
+    S.hc_off.assign(n, 0);
+    S.vt.clear();
+    S.ct.clear();
+    S.list.resize(n);
+    for (size_t i = 0; i < n; ++i) {
+        const HostProgram& h = *progs[i];
+        for (int32_t r = 0; r <= h.V; r += 64) S.vt.push_back({(int32_t)i, r});
+        for (int32_t r = 0; r < (int32_t)h.n_nogoods(); r += 64) S.ct.push_back({(int32_t)i, r});
+        S.list[i] = (int32_t)i;
+    }
+    S.off_w = take(sizeof(asp_scorer_weights));
+    S.off_hvo = take(8 * n);
+    S.off_hco = take(8 * n);
+    S.off_vt = take(sizeof(ScorerTile) * S.vt.size());
+    S.off_ct = take(sizeof(ScorerTile) * S.ct.size());
+    S.off_list = take(4 * n);
+    uint64_t atoms = 0;
+    for (auto* p : progs) atoms += (uint64_t)p->A;
+    S.off_lab = take(atoms + 1);
+    S.off_train = take(4 * (uint64_t)(3 * 65 + 66 + kMaxTrainSteps));
+    for (size_t i = 0; i < n; ++i) {
+        S.hv_off[i] = (int64_t)take(64 * ((uint64_t)progs[i]->V + 1));
+        S.hc_off[i] = (int64_t)take(64 * std::max<uint64_t>(1, progs[i]->n_nogoods()));
+    }
+    S.total = o;
+    S.planned = true;
+}
+
+ScorerArgs scorer_args(const std::vector<const HostProgram*>& progs, const Plan& P, uint8_t* arena,
+                       const ScorerPlan& S, uint8_t* ws);
+
+// Enqueue the scorer over every instance of the plan on stream s.
+int32_t run_scorer(const std::vector<const HostProgram*>& progs, const Plan& P, uint8_t* arena,
+                   ScorerPlan& S, const asp_scorer_weights* w, uint8_t* ws, uint64_t ws_bytes,
+                   hipStream_t s) {
+    int32_t rc = check_weights(w);
+    if (rc) return rc;
+    if (!ws || (uintptr_t)ws % kAlign) return fail(ASP_E_INVALID, "workspace must be 256-byte aligned");
+    scorer_plan(progs, S);
+    if (ws_bytes < S.total)
+        return fail(ASP_E_CAPACITY, "scorer workspace of " + std::to_string(ws_bytes) +
+                                        " bytes, need " + std::to_string(S.total));
+    DeviceInfo di = device_info();
+    if (!di.ok) return fail(ASP_E_DEVICE, "no HIP device");
+    S.w = *w;
+    HIPCHK(hipMemcpyAsync(ws + S.off_w, &S.w, sizeof(S.w), hipMemcpyHostToDevice, s));
+    if (S.uploaded_to != ws) {
+        HIPCHK(hipMemcpyAsync(ws + S.off_hvo, S.hv_off.data(), 8 * S.hv_off.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(ws + S.off_hco, S.hc_off.data(), 8 * S.hc_off.size(), hipMemcpyHostToDevice, s));
+        if (!S.vt.empty())
+            HIPCHK(hipMemcpyAsync(ws + S.off_vt, S.vt.data(), sizeof(ScorerTile) * S.vt.size(),
+                                  hipMemcpyHostToDevice, s));
+        if (!S.ct.empty())
+            HIPCHK(hipMemcpyAsync(ws + S.off_ct, S.ct.data(), sizeof(ScorerTile) * S.ct.size(),
+                                  hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(ws + S.off_list, S.list.data(), 4 * S.list.size(), hipMemcpyHostToDevice, s));
+        S.uploaded_to = ws;
+    }
+    ScorerArgs a = scorer_args(progs, P, arena, S, ws);
+    auto grid = [&](size_t tiles) { return (int)std::max<size_t>(1, std::min<size_t>(tiles, (size_t)di.cus * 8)); };
+    HIPCHK(launch_scorer_embed(a, grid(S.vt.size() + S.ct.size()), s));
+    for (int l = 0; l < ASP_SCORER_L; ++l) {
+        HIPCHK(launch_scorer_nogoods(a, l, grid(S.ct.size()), s));
+        HIPCHK(launch_scorer_vars(a, l, grid(S.vt.size()), s));
+    }
+    HIPCHK(launch_rule_scores(a, s));
+    return ASP_OK;
+}
+
+ScorerArgs scorer_args(const std::vector<const HostProgram*>& progs, const Plan& P, uint8_t* arena,
+                       const ScorerPlan& S, uint8_t* ws) {
+    ScorerArgs a{};
+    a.inst = (const InstDesc*)(arena + P.off_desc);
+    a.ng_off = (const int32_t*)(arena + P.off_ngo);
+    a.ng_lits = (const int32_t*)(arena + P.off_ngl);
+    a.map_off = (const int32_t*)(arena + P.off_mo);
+    a.map_ids = (const int32_t*)(arena + P.off_mi);
+    a.rule_head = (const int32_t*)(arena + P.off_rh);
+    a.w = ws + S.off_w;
+    a.hv_off = (const int64_t*)(ws + S.off_hvo);
+    a.hc_off = (const int64_t*)(ws + S.off_hco);
+    a.vtiles = (const ScorerTile*)(ws + S.off_vt);
+    a.ctiles = (const ScorerTile*)(ws + S.off_ct);
+    a.inst_list = (const int32_t*)(ws + S.off_list);
+    a.n_vtiles = (int32_t)S.vt.size();
+    a.n_ctiles = (int32_t)S.ct.size();
+    a.n_inst = (int32_t)progs.size();
+    a.ws = ws;
+    a.atom_score = (int32_t*)(arena + P.off_asc);
+    a.rule_score = (int32_t*)(arena + P.off_rs);
+    return a;
+}
+
 }  // namespace
 
 // ============================================================== C ABI
@@ -445,6 +642,8 @@ int32_t asp_load_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
     if (o.learned_cap_ng < 1 || o.learned_cap_lits < 1 || o.learned_cap_ng > (1 << 29) ||
         o.learned_cap_lits > ((int64_t)1 << 29))
         return fail(ASP_E_INVALID, "learned capacities must be in 1..2^29");
+    if (o.decision != ASP_DECISION_OCC && o.decision != ASP_DECISION_SCORE)
+        return fail(ASP_E_INVALID, "unknown decision heuristic");
     std::unique_ptr<asp_program> p(new asp_program());
     std::string err;
     int rc = encode_program(n_atoms, n_rules, head, body_off, body_lits, &p->hp, &err);
@@ -503,6 +702,41 @@ int32_t asp_bind_device(asp_program* p, void* dev_arena, uint64_t bytes, void* s
     rc = run_single(p, s, MODE_RESET, 0, 0, nullptr);
     if (rc) return rc;
     p->bound = true;
+    p->scores_ready = false;
+    return ASP_OK;
+}
+
+int32_t asp_set_scores(asp_program* p, const int32_t* scores, void* stream) {
+    if (!p || !p->bound) return fail(ASP_E_STATE, "program not bound to a device arena");
+    if (!scores) return fail(ASP_E_INVALID, "null scores");
+    int32_t rc = put_scores(p->plan, p->arena, 0, scores, (hipStream_t)stream);
+    if (rc) return rc;
+    p->scores_ready = true;
+    return ASP_OK;
+}
+
+int32_t asp_get_scores(asp_program* p, int32_t* scores, void* stream) {
+    if (!p || !p->bound) return fail(ASP_E_STATE, "program not bound to a device arena");
+    if (!scores) return fail(ASP_E_INVALID, "null scores");
+    return get_scores(p->plan, p->arena, 0, scores, (hipStream_t)stream);
+}
+
+int32_t asp_scorer_workspace(const asp_program* p, uint64_t* bytes) {
+    if (!p || !bytes) return fail(ASP_E_INVALID, "null program or output");
+    ScorerPlan S;
+    scorer_plan({&p->hp}, S);
+    *bytes = S.total;
+    return ASP_OK;
+}
+
+int32_t asp_score_program(asp_program* p, const asp_scorer_weights* w, void* ws, uint64_t ws_bytes,
+                          void* stream) {
+    if (!p || !p->bound) return fail(ASP_E_STATE, "program not bound to a device arena");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t rc = run_scorer({&p->hp}, p->plan, p->arena, p->scorer, w, (uint8_t*)ws, ws_bytes, s);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    p->scores_ready = true;
     return ASP_OK;
 }
 
@@ -570,6 +804,8 @@ int32_t asp_analyze_conflict(asp_program* p, void* stream, const asp_limits* lim
 int32_t asp_run_steps(asp_program* p, void* stream, const asp_limits* lim, int64_t n_steps,
                       asp_stats* stats) {
     if (!p || !p->bound) return fail(ASP_E_STATE, "program not bound to a device arena");
+    if (p->opt.decision == ASP_DECISION_SCORE && !p->scores_ready)
+        return fail(ASP_E_STATE, "decision scores not set");
     hipStream_t s = (hipStream_t)stream;
     int32_t rc = run_single(p, s, MODE_STEPS, 0xff, n_steps < 0 ? INT64_MAX : n_steps, lim);
     if (rc) return rc;
@@ -583,6 +819,8 @@ int32_t asp_run_steps(asp_program* p, void* stream, const asp_limits* lim, int64
 int32_t asp_solve(asp_program* p, void* stream, const asp_limits* lim, uint8_t* model,
                   asp_stats* stats) {
     if (!p || !p->bound) return fail(ASP_E_STATE, "program not bound to a device arena");
+    if (p->opt.decision == ASP_DECISION_SCORE && !p->scores_ready)
+        return fail(ASP_E_STATE, "decision scores not set");
     hipStream_t s = (hipStream_t)stream;
     DeviceInfo di = device_info();
     int32_t rc = check_launch(p->plan, di);
@@ -618,6 +856,9 @@ int32_t asp_state_export(asp_program* p, void* stream, asp_state* st) {
     st->learned_lits = k.learned_lits;
     st->initialised = k.init_done;
     st->status = k.status;
+    st->score_mode = k.use_score;
+    st->consec = k.consec;
+    st->dec_open = k.dec_open;
     ctrl_stats(k, &st->stats);
     if (!st->val) return ASP_OK;
     const SlotLayout L = slot0(p);
@@ -733,6 +974,11 @@ int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
     if (st->pending >= nS + nL) return fail(ASP_E_INVALID, "pending conflict id");
     k.status = ASP_RUNNING;
     k.init_done = st->initialised ? 1 : 0;
+    if (st->score_mode && p->opt.decision != ASP_DECISION_SCORE)
+        return fail(ASP_E_INVALID, "score mode on a program loaded for occurrence decisions");
+    k.use_score = st->score_mode ? 1 : 0;
+    k.consec = st->consec;
+    k.dec_open = st->dec_open ? 1 : 0;
     k.last_step = st->stats.last_step;
     k.learned_lits = st->learned_lits;
     k.rounds = st->stats.rounds;
@@ -790,7 +1036,8 @@ int32_t asp_batch_create(int32_t n, asp_program* const* progs, const asp_schedul
         if (!progs[i]) return fail(ASP_E_INVALID, "null program in batch");
         const asp_options& o = progs[i]->opt;
         if (o.W != b->opt.W || o.gate != b->opt.gate || o.learned_cap_ng != b->opt.learned_cap_ng ||
-            o.learned_cap_lits != b->opt.learned_cap_lits)
+            o.learned_cap_lits != b->opt.learned_cap_lits || o.decision != b->opt.decision ||
+            o.fallback_after != b->opt.fallback_after)
             return fail(ASP_E_INVALID, "batch programs must share their options");
         b->progs.push_back(&progs[i]->hp);
     }
@@ -810,11 +1057,94 @@ int32_t asp_batch_bind(asp_batch* b, void* dev_arena, uint64_t bytes, void* stre
     int32_t rc = upload_static(b->progs, b->plan, b->arena, (hipStream_t)stream);
     if (rc) return rc;
     b->bound = true;
+    b->ready.assign(b->plan.n, 0);
+    b->n_ready = 0;
+    return ASP_OK;
+}
+
+int32_t asp_batch_set_scores(asp_batch* b, int32_t i, const int32_t* scores, void* stream) {
+    if (!b || !b->bound) return fail(ASP_E_STATE, "batch not bound");
+    if (i < 0 || i >= b->plan.n || !scores) return fail(ASP_E_INVALID, "bad instance or null scores");
+    int32_t rc = put_scores(b->plan, b->arena, i, scores, (hipStream_t)stream);
+    if (rc) return rc;
+    if (!b->ready[i]) {
+        b->ready[i] = 1;
+        b->n_ready += 1;
+    }
+    return ASP_OK;
+}
+
+int32_t asp_batch_get_scores(asp_batch* b, int32_t i, int32_t* scores, void* stream) {
+    if (!b || !b->bound) return fail(ASP_E_STATE, "batch not bound");
+    if (i < 0 || i >= b->plan.n || !scores) return fail(ASP_E_INVALID, "bad instance or null scores");
+    return get_scores(b->plan, b->arena, i, scores, (hipStream_t)stream);
+}
+
+int32_t asp_batch_scorer_workspace(const asp_batch* b, uint64_t* bytes) {
+    if (!b || !bytes) return fail(ASP_E_INVALID, "null batch or output");
+    ScorerPlan S;
+    scorer_plan(b->progs, S);
+    *bytes = S.total;
+    return ASP_OK;
+}
+
+int32_t asp_score_batch(asp_batch* b, const asp_scorer_weights* w, void* ws, uint64_t ws_bytes,
+                        void* stream) {
+    if (!b || !b->bound) return fail(ASP_E_STATE, "batch not bound");
+    int32_t rc = run_scorer(b->progs, b->plan, b->arena, b->scorer, w, (uint8_t*)ws, ws_bytes,
+                            (hipStream_t)stream);
+    if (rc) return rc;
+    b->ready.assign(b->plan.n, 1);
+    b->n_ready = b->plan.n;
+    return ASP_OK;
+}
+
+int32_t asp_batch_train_readout(asp_batch* b, const asp_scorer_weights* w, void* ws,
+                                uint64_t ws_bytes, const int8_t* labels, int32_t steps, float lr,
+                                float* wb_out, float* loss_out, void* stream) {
+    if (!b || !b->bound) return fail(ASP_E_STATE, "batch not bound");
+    if (!labels || !wb_out) return fail(ASP_E_INVALID, "null labels or output");
+    if (steps < 1 || steps > kMaxTrainSteps) return fail(ASP_E_INVALID, "steps must be in 1..4096");
+    if (!(lr > 0.f)) return fail(ASP_E_INVALID, "learning rate must be positive");
+    hipStream_t s = (hipStream_t)stream;
+    // forward pass: the last layer's codes stay in the workspace
+    int32_t rc = run_scorer(b->progs, b->plan, b->arena, b->scorer, w, (uint8_t*)ws, ws_bytes, s);
+    if (rc) return rc;
+    const ScorerPlan& S = b->scorer;
+    uint8_t* W8 = (uint8_t*)ws;
+    const uint64_t atoms = (uint64_t)b->plan.tot_model;
+    int64_t n_lab = 0;
+    for (uint64_t i = 0; i < atoms; ++i) n_lab += labels[i] >= 0 ? 1 : 0;
+    if (n_lab == 0) return fail(ASP_E_INVALID, "no labelled atom");
+    std::vector<float> init(3 * 65 + 66, 0.f);
+    for (int j = 0; j < 64; ++j) init[j] = wb_out[j];   // caller's starting point
+    init[64] = wb_out[64];
+    float* T = (float*)(W8 + S.off_train);
+    if (atoms) HIPCHK(hipMemcpyAsync(W8 + S.off_lab, labels, atoms, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(T, init.data(), 4 * init.size(), hipMemcpyHostToDevice, s));
+    TrainArgs t{};
+    t.labels = (const int8_t*)(W8 + S.off_lab);
+    t.wb = T;
+    t.m = T + 65;
+    t.v = T + 130;
+    t.grad = T + 195;
+    t.loss = T + 261;
+    t.inv_n = 1.f / (float)n_lab;
+    t.lr = lr;
+    DeviceInfo di = device_info();
+    ScorerArgs a = scorer_args(b->progs, b->plan, b->arena, S, W8);
+    const int grid = (int)std::max<size_t>(1, std::min<size_t>(S.vt.size(), (size_t)di.cus * 4));
+    HIPCHK(launch_readout_train(a, t, steps, grid, s));
+    HIPCHK(hipMemcpyAsync(wb_out, T, 4 * 65, hipMemcpyDeviceToHost, s));
+    if (loss_out) HIPCHK(hipMemcpyAsync(loss_out, t.loss, 4 * (size_t)steps, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     return ASP_OK;
 }
 
 int32_t asp_solve_batch(asp_batch* b, void* stream, const asp_limits* lim) {
     if (!b || !b->bound) return fail(ASP_E_STATE, "batch not bound");
+    if (b->opt.decision == ASP_DECISION_SCORE && b->n_ready < b->plan.n)
+        return fail(ASP_E_STATE, "decision scores not set for every instance");
     hipStream_t s = (hipStream_t)stream;
     DeviceInfo di = device_info();
     int32_t rc = check_launch(b->plan, di);

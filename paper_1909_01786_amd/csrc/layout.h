@@ -4,6 +4,8 @@
 //   [static]  per-instance descriptors, the instance order, and every
 //             instance's completion nogoods (CSR), literal->nogood map (CSR),
 //             rule table and rule bodies, packed one instance after another;
+//   [scores]  per-instance decision scores of atoms and of rules (the score
+//             of each rule's head), written before a score-driven search;
 //   [results] verdicts, per-instance counters, model bytes;
 //   [slots]   one dynamic search state per instance, sized for it.
 //
@@ -26,6 +28,7 @@ struct InstDesc {
     int64_t rb_off;    // into rb_off[] (Rh+1 entries, values relative to rb_lits)
     int64_t rb_lits;   // into rb_lits[] (rule bodies, +a body+ / -a body-)
     int64_t model;     // byte offset of this instance's model in models[]
+    int64_t ascore;    // into atom_score[] (A+1 entries, [0] unused)
     int32_t A, Rh, V, n_static;
     int32_t u0, u1;    // ids of the unit nogoods: [u0, u1)
     int32_t has_empty; // an empty nogood (empty-body constraint) exists
@@ -37,7 +40,8 @@ struct InstDesc {
 struct SlotCtrl {
     int32_t inst, cdl, qh, qt;
     int32_t n_learned, pool_top, pending, pend_kind;  // pend_kind 0 none, 1 round, 2 gate
-    int32_t status, init_done, last_step, pad0;
+    int32_t status, init_done, last_step, use_score;
+    int32_t consec, dec_open, pad1, pad2;    // learned-Decision fallback state
     int64_t learned_lits;
     int64_t rounds, visits, checks, props, decisions, conflicts, learned, learned_len,
             gate_fail, completes;
@@ -106,6 +110,8 @@ enum StepKind : int32_t {
     STEP_COMPLETE = 5, STEP_GATE = 6, STEP_DONE = 7
 };
 
+enum Decision : int32_t { DECISION_OCC = 0, DECISION_SCORE = 1 };
+
 enum Mode : int32_t {
     MODE_SOLVE = 0,      // workgroup b solves instance order[first + b] to a verdict
     MODE_STEPS = 1,      // instance 0: run up to max_steps steps
@@ -130,6 +136,7 @@ struct KArgs {
     const int32_t* map_ids;
     const int32_t* rule_head;
     const int32_t* rule_occ;
+    const int32_t* rule_score;   // score of each rule's head (score-driven Decision)
     const int32_t* rb_off;
     const int32_t* rb_lits;
     uint8_t* slots;              // base of the state slots
@@ -138,6 +145,8 @@ struct KArgs {
     DevStats* stats;
     uint8_t* models;
     int32_t W, gate_mode;
+    int32_t decision;            // DECISION_OCC or DECISION_SCORE
+    int32_t fallback_after;      // conflicts in a row before scores give way; <0 never
     int32_t words;               // LDS words per 2-bit map (this launch's largest V)
     int32_t step_mask;           // MODE_STEPS: kinds allowed to run (bit k)
     int64_t max_steps;           // MODE_STEPS: steps to run; MODE_SOLVE: guard

@@ -1,0 +1,485 @@
+// scorer.hip -- the learned Decision's atom scorer for gfx950 (CDNA4, wave64).
+//
+// The Decision of Sect. 2 picks an applicable rule by a score of its head.
+// The learned form scores atoms with a message-passing network over the
+// bipartite graph of variables and static nogoods (edges: nogood literals,
+// with their sign).  The network is quantisation-aware so that it is exact:
+// activations are integer codes 0..255 and weights integer codes -127..127,
+// both held as bfloat16; a 64-term product of them is an integer below 2^21,
+// exact in the float32 accumulator of the matrix cores whatever the order of
+// its sums.  Edge sums are integer atomics in LDS (order-free as well), and
+// the requantisation act(z) = min(255, (z + 256) >> 9) for z > 0 is integer.
+//
+// Work is cut into tiles of 64 rows of one instance (variables, or static
+// nogoods), one workgroup of four waves per tile, tiles taken grid-stride so
+// each workgroup stages the layer's weights into LDS once.  A tile's edges
+// are taken 64 at a time: their source rows are gathered into an LDS operand
+// tile, multiplied by both sign matrices on the matrix cores (32x32x8 bf16
+// blocks, two per wave), and each product row is added into its owner's
+// int64 accumulator when its sign matches.  The epilogue multiplies the
+// tile's own rows by the self matrix, adds the normalised edge sum and the
+// bias, requantises, and stores the 64 codes per row.
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/asp.h"
+#include "scorer.h"
+
+namespace asp {
+namespace {
+
+#define DEV __device__ __forceinline__
+
+constexpr int H = ASP_SCORER_H;   // hidden width
+constexpr int F = ASP_SCORER_F;   // input features
+constexpr int TR = 64;            // rows per tile
+constexpr int NT = 256;           // threads per workgroup
+constexpr int LD = H + 4;         // LDS row stride of bf16 operand tiles
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+DEV const uint16_t* wmat(const ScorerArgs& a, size_t off) { return (const uint16_t*)(a.w + off); }
+DEV const int32_t* wvec(const ScorerArgs& a, size_t off) { return (const int32_t*)(a.w + off); }
+
+// An integer-valued bfloat16 as int (exact for the codes used here).
+DEV int bf16_int(uint16_t b) { return (int)__uint_as_float((uint32_t)b << 16); }
+// Activation code 0..255 as bfloat16 bits (exact).
+DEV uint16_t code_bf16(uint32_t code) { return (uint16_t)(__float_as_uint((float)code) >> 16); }
+
+DEV int act(long long z) { return z <= 0 ? 0 : (int)(((z + 256) >> 9) < 255 ? ((z + 256) >> 9) : 255); }
+
+// s / 2^k rounded half up (arithmetic shift), k = ceil(log2 n); n <= 1: s.
+DEV long long norm_sum(long long s, int n) {
+    if (n <= 1) return s;
+    const int k = 32 - __clz(n - 1);
+    return (s + (1LL << (k - 1))) >> k;
+}
+
+// One 32x32 block: 32 rows of an operand tile (stride LD) times 32 output
+// columns given as rows of a transposed weight tile (stride LD), K = 64.
+DEV v16f mma_block(const uint16_t* A, const uint16_t* BT, int lane) {
+    v16f acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    const int i = lane & 31, kh = (lane >> 5) * 4;
+#pragma unroll
+    for (int k0 = 0; k0 < H; k0 += 8) {
+        const v4s x = *(const v4s*)(A + i * LD + k0 + kh);
+        const v4s y = *(const v4s*)(BT + i * LD + k0 + kh);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(x, y, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Row of output element r of a 32x32 block (its column is lane % 32).
+DEV int blk_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// BT[j][k] = M[k][j] for a [64][64] matrix M held in global memory.
+DEV void stage_t(uint16_t* BT, const uint16_t* M, int tid) {
+    for (int idx = tid; idx < H * H; idx += NT) {
+        const int k = idx >> 6, j = idx & 63;
+        BT[j * LD + k] = M[k * H + j];
+    }
+}
+
+// 16 activation codes from global memory as bfloat16 into an operand row.
+DEV void load_codes16(uint16_t* dst, const uint8_t* src) {
+    const uint4 q = *(const uint4*)src;
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dst[4 * b + t] = code_bf16((w[b] >> (8 * t)) & 255u);
+}
+
+DEV void zero16(uint16_t* dst) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) dst[t] = 0;
+}
+
+// LDS of the layer kernels (dynamic, 8-byte aligned base).
+struct LayerLds {
+    unsigned long long* acc;   // [TR][H] edge sums
+    uint16_t* wt;              // [2H][LD] both sign matrices, transposed
+    uint16_t* st;              // [H][LD] self matrix, transposed
+    uint16_t* opa;             // [TR][LD] operand tile; the output codes alias it
+    int32_t* start;            // [2TR+1] segment starts
+    int32_t* own;              // [TR] owner row of each gathered edge
+    int32_t* pos;              // [TR] 1 if the edge's literal is positive
+    int32_t* bias;             // [H]
+};
+
+constexpr size_t kLayerLds = sizeof(unsigned long long) * TR * H + sizeof(uint16_t) * 2 * H * LD +
+                             sizeof(uint16_t) * H * LD + sizeof(uint16_t) * TR * LD +
+                             sizeof(int32_t) * (2 * TR + 1 + TR + TR + H) + 16;
+
+DEV LayerLds carve(unsigned long long* base) {
+    LayerLds L;
+    unsigned char* p = (unsigned char*)base;
+    L.acc = (unsigned long long*)p; p += sizeof(unsigned long long) * TR * H;
+    L.wt = (uint16_t*)p; p += sizeof(uint16_t) * 2 * H * LD;
+    L.st = (uint16_t*)p; p += sizeof(uint16_t) * H * LD;
+    L.opa = (uint16_t*)p; p += sizeof(uint16_t) * TR * LD;
+    L.start = (int32_t*)p; p += sizeof(int32_t) * (2 * TR + 1);
+    L.own = (int32_t*)p; p += sizeof(int32_t) * TR;
+    L.pos = (int32_t*)p; p += sizeof(int32_t) * TR;
+    L.bias = (int32_t*)p;
+    return L;
+}
+
+// Multiply the gathered operand rows [0, ne) by both sign matrices and add
+// each product row into its owner's accumulator when the sign matches.
+DEV void edge_products(const LayerLds& L, int ne, int tid) {
+    const int w = tid >> 6, lane = tid & 63;
+    const int rb = w & 1, sg = w >> 1;            // sg 0: positive matrix, 1: negative
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const v16f o = mma_block(L.opa + 32 * rb * LD, L.wt + (sg * H + cb * 32) * LD, lane);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 32 * rb + blk_row(r, lane);
+            if (row < ne && L.pos[row] == 1 - sg)
+                atomicAdd(&L.acc[L.own[row] * H + cb * 32 + (lane & 31)],
+                          (unsigned long long)(long long)(int)o[r]);
+        }
+    }
+}
+
+// Epilogue: own rows (already in the operand tile) times the self matrix,
+// plus the normalised edge sums and the bias, requantised into `out` rows.
+// seg_len(row) gives the normaliser; rows >= rows_n are not written.
+template <class Len>
+DEV void finish_tile(const LayerLds& L, int rows_n, Len seg_len, int zero_row, uint8_t* out,
+                     int tid) {
+    const int w = tid >> 6, lane = tid & 63;
+    const int rb = w & 1, cb = w >> 1;
+    const v16f o = mma_block(L.opa + 32 * rb * LD, L.st + 32 * cb * LD, lane);
+    __syncthreads();                               // operand tile is read; codes may alias it
+    uint8_t* codes = (uint8_t*)L.opa;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = 32 * rb + blk_row(r, lane), col = 32 * cb + (lane & 31);
+        if (row < rows_n) {
+            const long long z = (long long)(int)o[r] +
+                                norm_sum((long long)L.acc[row * H + col], seg_len(row)) +
+                                L.bias[col];
+            codes[row * H + col] = row == zero_row ? (uint8_t)0 : (uint8_t)act(z);
+        }
+    }
+    __syncthreads();
+    const int row = tid >> 2, part = tid & 3;
+    if (row < rows_n) *(uint4*)(out + (size_t)row * H + part * 16) = *(const uint4*)(codes + row * H + part * 16);
+}
+
+// ------------------------------------------------------------------ kernels
+__global__ __launch_bounds__(NT) void k_embed(ScorerArgs a) {
+    __shared__ int sE[F * H];
+    __shared__ int sB[H];
+    __shared__ int sX[TR][F];
+    const int tid = threadIdx.x;
+    const int total = a.n_vtiles + a.n_ctiles;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const bool var = t < a.n_vtiles;
+        const ScorerTile tl = var ? a.vtiles[t] : a.ctiles[t - a.n_vtiles];
+        const InstDesc& d = a.inst[tl.inst];
+        const uint16_t* E = wmat(a, var ? offsetof(asp_scorer_weights, Ev) : offsetof(asp_scorer_weights, Ec));
+        const int32_t* eb = wvec(a, var ? offsetof(asp_scorer_weights, ev) : offsetof(asp_scorer_weights, ec));
+        for (int i = tid; i < F * H; i += NT) sE[i] = bf16_int(E[i]);
+        for (int i = tid; i < H; i += NT) sB[i] = eb[i];
+        const int nrows = var ? min(TR, d.V + 1 - tl.row0) : min(TR, d.n_static - tl.row0);
+        if (tid < TR) {
+            int x[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) x[f] = 0;
+            const int r = tl.row0 + tid;
+            if (tid < nrows && var && r >= 1) {
+                const int32_t* MO = a.map_off + d.map_off;
+                const int dp = MO[2 * r + 1] - MO[2 * r], dn = MO[2 * r + 2] - MO[2 * r + 1];
+                x[0] = 32;
+                x[1] = r <= d.A ? 32 : 0;
+                if (r > d.A) x[2 + (r - d.A - 1) % 3] = 32;
+                x[5] = (32 + (1 + dp) / 2) / (1 + dp);
+                x[6] = (32 + (1 + dn) / 2) / (1 + dn);
+            } else if (tid < nrows && !var) {
+                const int32_t* NO = a.ng_off + d.ng_off;
+                const int32_t* NL = a.ng_lits + d.ng_lits;
+                const int b = NO[r], len = NO[r + 1] - b;
+                int np = 0;
+                for (int q = 0; q < len; ++q) np += NL[b + q] > 0 ? 1 : 0;
+                x[0] = 32;
+                x[1] = len > 0 ? (32 + len / 2) / len : 0;
+                x[2] = len == 1 ? 32 : 0;
+                x[3] = len == 2 ? 32 : 0;
+                x[4] = len == 3 ? 32 : 0;
+                x[5] = len >= 4 ? 32 : 0;
+                x[6] = len > 0 ? (32 * np + len / 2) / len : 0;
+            }
+#pragma unroll
+            for (int f = 0; f < F; ++f) sX[tid][f] = x[f];
+        }
+        __syncthreads();
+        const int row = tid >> 2, c0 = (tid & 3) * 16;
+        if (row < nrows) {
+            uint8_t* out = a.ws + (var ? a.hv_off[tl.inst] : a.hc_off[tl.inst]) +
+                           (size_t)(tl.row0 + row) * H + c0;
+            const bool zero = var && tl.row0 + row == 0;
+            uint32_t pk[4] = {0u, 0u, 0u, 0u};
+            for (int j = 0; j < 16; ++j) {
+                long long z = sB[c0 + j];
+#pragma unroll
+                for (int f = 0; f < F; ++f) z += (long long)sX[row][f] * sE[f * H + c0 + j];
+                const uint32_t code = zero ? 0u : (uint32_t)act(z);
+                pk[j >> 2] |= code << (8 * (j & 3));
+            }
+            *(uint4*)out = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+        }
+        __syncthreads();
+    }
+}
+
+// Nogood update of layer l: hc = act(hc S + norm(sum hv P | hv N, |c|) + bc).
+__global__ __launch_bounds__(NT) void k_nogoods(ScorerArgs a, int l) {
+    HIP_DYNAMIC_SHARED(unsigned long long, smem);
+    const LayerLds L = carve(smem);
+    const int tid = threadIdx.x;
+    const size_t HH = (size_t)H * H;
+    stage_t(L.wt, wmat(a, offsetof(asp_scorer_weights, P)) + l * HH, tid);
+    stage_t(L.wt + H * LD, wmat(a, offsetof(asp_scorer_weights, N)) + l * HH, tid);
+    stage_t(L.st, wmat(a, offsetof(asp_scorer_weights, S)) + l * HH, tid);
+    for (int i = tid; i < H; i += NT) L.bias[i] = wvec(a, offsetof(asp_scorer_weights, bc))[l * H + i];
+    for (int t = blockIdx.x; t < a.n_ctiles; t += gridDim.x) {
+        const ScorerTile tl = a.ctiles[t];
+        const InstDesc& d = a.inst[tl.inst];
+        const int rows = min(TR, d.n_static - tl.row0);
+        const int32_t* NO = a.ng_off + d.ng_off + tl.row0;
+        const int32_t* NL = a.ng_lits + d.ng_lits;
+        const uint8_t* hv = a.ws + a.hv_off[tl.inst];
+        uint8_t* hc = a.ws + a.hc_off[tl.inst] + (size_t)tl.row0 * H;
+        for (int i = tid; i <= rows; i += NT) L.start[i] = NO[i];
+        for (int i = tid; i < TR * H; i += NT) L.acc[i] = 0ull;
+        __syncthreads();
+        const int e0 = L.start[0], e1 = L.start[rows];
+        const int er = tid >> 2, part = tid & 3;
+        for (int eb = e0; eb < e1; eb += TR) {
+            const int ne = min(TR, e1 - eb);
+            if (er < ne) {
+                const int lit = NL[eb + er];
+                const int v = lit < 0 ? -lit : lit;
+                load_codes16(L.opa + er * LD + part * 16, hv + (size_t)v * H + part * 16);
+                if (part == 0) {
+                    int lo = 0, hi = rows - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (L.start[mid] <= eb + er) lo = mid; else hi = mid - 1;
+                    }
+                    L.own[er] = lo;
+                    L.pos[er] = lit > 0 ? 1 : 0;
+                }
+            } else {
+                zero16(L.opa + er * LD + part * 16);
+            }
+            __syncthreads();
+            edge_products(L, ne, tid);
+            __syncthreads();
+        }
+        if (er < rows) load_codes16(L.opa + er * LD + part * 16, hc + (size_t)er * H + part * 16);
+        else zero16(L.opa + er * LD + part * 16);
+        __syncthreads();
+        finish_tile(L, rows, [&](int row) { return L.start[row + 1] - L.start[row]; }, -1, hc, tid);
+        __syncthreads();
+    }
+}
+
+// Variable update of layer l: hv = act(hv T + norm(sum hc Q | hc R, deg v) + bv);
+// the last layer also writes each atom's score hv . wo + bo.
+__global__ __launch_bounds__(NT) void k_vars(ScorerArgs a, int l, int last) {
+    HIP_DYNAMIC_SHARED(unsigned long long, smem);
+    const LayerLds L = carve(smem);
+    __shared__ int sWo[H];
+    const int tid = threadIdx.x;
+    const size_t HH = (size_t)H * H;
+    stage_t(L.wt, wmat(a, offsetof(asp_scorer_weights, Q)) + l * HH, tid);
+    stage_t(L.wt + H * LD, wmat(a, offsetof(asp_scorer_weights, R)) + l * HH, tid);
+    stage_t(L.st, wmat(a, offsetof(asp_scorer_weights, T)) + l * HH, tid);
+    for (int i = tid; i < H; i += NT) {
+        L.bias[i] = wvec(a, offsetof(asp_scorer_weights, bv))[l * H + i];
+        sWo[i] = wvec(a, offsetof(asp_scorer_weights, wo))[i];
+    }
+    const int bo = *wvec(a, offsetof(asp_scorer_weights, bo));
+    for (int t = blockIdx.x; t < a.n_vtiles; t += gridDim.x) {
+        const ScorerTile tl = a.vtiles[t];
+        const InstDesc& d = a.inst[tl.inst];
+        const int rows = min(TR, d.V + 1 - tl.row0);
+        const int32_t* MO = a.map_off + d.map_off + 2 * tl.row0;
+        const int32_t* MI = a.map_ids + d.map_ids;
+        const uint8_t* hc = a.ws + a.hc_off[tl.inst];
+        uint8_t* hv = a.ws + a.hv_off[tl.inst] + (size_t)tl.row0 * H;
+        const int nseg = 2 * rows;
+        for (int i = tid; i <= nseg; i += NT) L.start[i] = MO[i];
+        for (int i = tid; i < TR * H; i += NT) L.acc[i] = 0ull;
+        __syncthreads();
+        const int e0 = L.start[0], e1 = L.start[nseg];
+        const int er = tid >> 2, part = tid & 3;
+        for (int eb = e0; eb < e1; eb += TR) {
+            const int ne = min(TR, e1 - eb);
+            if (er < ne) {
+                const int c = MI[eb + er];
+                load_codes16(L.opa + er * LD + part * 16, hc + (size_t)c * H + part * 16);
+                if (part == 0) {
+                    int lo = 0, hi = nseg - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (L.start[mid] <= eb + er) lo = mid; else hi = mid - 1;
+                    }
+                    L.own[er] = lo >> 1;
+                    L.pos[er] = (lo & 1) ? 0 : 1;
+                }
+            } else {
+                zero16(L.opa + er * LD + part * 16);
+            }
+            __syncthreads();
+            edge_products(L, ne, tid);
+            __syncthreads();
+        }
+        if (er < rows) load_codes16(L.opa + er * LD + part * 16, hv + (size_t)er * H + part * 16);
+        else zero16(L.opa + er * LD + part * 16);
+        __syncthreads();
+        finish_tile(L, rows, [&](int row) { return L.start[2 * row + 2] - L.start[2 * row]; },
+                    tl.row0 == 0 ? 0 : -1, hv, tid);
+        if (last && tid < rows) {
+            const int v = tl.row0 + tid;
+            if (v <= d.A) {
+                const uint8_t* codes = (const uint8_t*)L.opa + tid * H;
+                int s = bo;
+                for (int j = 0; j < H; ++j) s += (int)codes[j] * sWo[j];
+                a.atom_score[d.ascore + v] = v == 0 ? 0 : s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// rule_score[r] = atom_score[head(r)] for every headed rule of the listed
+// instances.
+__global__ __launch_bounds__(NT) void k_rule_scores(ScorerArgs a) {
+    const int n = a.inst_list ? a.n_inst : 1;
+    for (int b = blockIdx.x; b < n; b += gridDim.x) {
+        const InstDesc& d = a.inst[a.inst_list ? a.inst_list[b] : a.single];
+        for (int j = threadIdx.x; j < d.Rh; j += NT)
+            a.rule_score[d.rules + j] = a.atom_score[d.ascore + a.rule_head[d.rules + j]];
+    }
+}
+
+// ------------------------------------------------------- readout training
+// Logistic regression of the readout on the last layer's codes: for every
+// labelled atom v (label 1: true in the answer set found, 0: false),
+// logit = sum_j (hv_j / 256) w_j + b, and the gradient of the mean binary
+// cross-entropy is (sigmoid(logit) - y) (hv_j / 256, 1).  Sums go through
+// float atomics in LDS, then one global atomic per workgroup and element.
+__global__ __launch_bounds__(NT) void k_readout_grad(ScorerArgs a, TrainArgs t) {
+    __shared__ float sg[H + 2];
+    __shared__ float sw[H + 1];
+    const int tid = threadIdx.x;
+    if (tid < H + 2) sg[tid] = 0.f;
+    if (tid < H + 1) sw[tid] = t.wb[tid];
+    __syncthreads();
+    for (int ti = blockIdx.x; ti < a.n_vtiles; ti += gridDim.x) {
+        const ScorerTile tl = a.vtiles[ti];
+        const InstDesc& d = a.inst[tl.inst];
+        const int v = tl.row0 + (tid & 63);
+        // four row groups of 16 columns: lanes of one row share its logit
+        const int part = tid >> 6;
+        float lg = 0.f, y = -1.f;
+        const uint8_t* hv = a.ws + a.hv_off[tl.inst] + (size_t)v * H;
+        if (v >= 1 && v <= d.A && v <= d.V) {
+            const int8_t lab = t.labels[d.model + v - 1];
+            if (lab >= 0) {
+                y = (float)lab;
+                for (int j = 0; j < H; ++j) lg += (float)hv[j] * (1.f / 256.f) * sw[j];
+                lg += sw[H];
+            }
+        }
+        if (y >= 0.f) {
+            const float p = 1.f / (1.f + __expf(-lg));
+            const float g = (p - y) * t.inv_n;
+            for (int j = part * 16; j < part * 16 + 16; ++j)
+                atomicAdd(&sg[j], g * (float)hv[j] * (1.f / 256.f));
+            if (part == 0) {
+                atomicAdd(&sg[H], g);
+                // binary cross-entropy, stable form
+                const float ce = fmaxf(lg, 0.f) - lg * y + __logf(1.f + __expf(-fabsf(lg)));
+                atomicAdd(&sg[H + 1], ce * t.inv_n);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < H + 2) atomicAdd(&t.grad[tid], sg[tid]);
+}
+
+// Adam step on (w, b) from the summed gradient; clears the gradient and
+// records the loss of this step.
+__global__ void k_readout_adam(TrainArgs t, int step) {
+    const int i = threadIdx.x;
+    if (i < H + 1) {
+        const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+        const float g = t.grad[i];
+        t.m[i] = b1 * t.m[i] + (1.f - b1) * g;
+        t.v[i] = b2 * t.v[i] + (1.f - b2) * g * g;
+        const float mh = t.m[i] / (1.f - __powf(b1, (float)(step + 1)));
+        const float vh = t.v[i] / (1.f - __powf(b2, (float)(step + 1)));
+        t.wb[i] -= t.lr * mh / (sqrtf(vh) + eps);
+    }
+    __syncthreads();
+    if (i == 0) t.loss[step] = t.grad[H + 1];
+    __syncthreads();
+    if (i < H + 2) t.grad[i] = 0.f;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- launchers
+hipError_t launch_scorer_embed(const ScorerArgs& a, int grid, hipStream_t s) {
+    if (a.n_vtiles + a.n_ctiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_embed, dim3(grid), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scorer_nogoods(const ScorerArgs& a, int layer, int grid, hipStream_t s) {
+    if (a.n_ctiles == 0) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_nogoods,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLayerLds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_nogoods, dim3(grid), dim3(NT), kLayerLds, s, a, layer);
+    return hipGetLastError();
+}
+
+hipError_t launch_scorer_vars(const ScorerArgs& a, int layer, int grid, hipStream_t s) {
+    if (a.n_vtiles == 0) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_vars,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLayerLds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_vars, dim3(grid), dim3(NT), kLayerLds, s, a, layer,
+                       layer == ASP_SCORER_L - 1 ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout_train(const ScorerArgs& a, const TrainArgs& t, int steps, int grid,
+                                hipStream_t s) {
+    for (int k = 0; k < steps; ++k) {
+        hipLaunchKernelGGL(k_readout_grad, dim3(grid), dim3(NT), 0, s, a, t);
+        hipLaunchKernelGGL(k_readout_adam, dim3(1), dim3(128), 0, s, t, k);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rule_scores(const ScorerArgs& a, hipStream_t s) {
+    const int n = a.inst_list ? a.n_inst : 1;
+    if (n == 0) return hipSuccess;
+    const int grid = n < 4096 ? n : 4096;
+    hipLaunchKernelGGL(k_rule_scores, dim3(grid), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace asp

@@ -52,6 +52,7 @@ constexpr int kMaxWaves = 16;
 struct Ctl {
     int32_t inst, A, Rh, V, nS, u0, u1, has_empty;
     int32_t cdl, qh, qt, n_learned, pend_kind, pending, status, init_done, last_step, pool_top;
+    int32_t use_score, consec, dec_open;   // score-driven Decision and its fallback
     int64_t learned_lits, rounds, props, decisions, conflicts, learned, learned_len, gate_fail,
             completes, steps, visits, checks;
     uint64_t hash;
@@ -68,7 +69,7 @@ struct Scr {
 
 struct Ctx {
     // per-instance static arrays
-    const int32_t *NO, *NL, *MO, *MI, *RH, *RO, *RBO, *RBL;
+    const int32_t *NO, *NL, *MO, *MI, *RH, *RO, *RS, *RBO, *RBL;
     // per-slot arrays
     SlotCtrl* ctrl;
     int8_t* val8;
@@ -81,6 +82,7 @@ struct Ctx {
     unsigned long long* sB;
     Scr* scr;
     int32_t W, T, tid, lane, wid, nw;
+    int32_t decision, fallback_after;
     unsigned long long my_visits, my_checks;
 };
 
@@ -254,6 +256,7 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     c.MI = a.map_ids + d.map_ids;
     c.RH = a.rule_head + d.rules;
     c.RO = a.rule_occ + d.rules;
+    c.RS = a.rule_score + d.rules;
     c.RBO = a.rb_off + d.rb_off;
     c.RBL = a.rb_lits + d.rb_lits;
     c.ctrl = (SlotCtrl*)(slot + lay.ctrl);
@@ -309,6 +312,9 @@ DEV void reset_search(Ctx& c, Ctl& k) {
     k.visits = k.checks = 0;
     k.hash = FNV_BASIS;
     k.steps = 0;
+    k.use_score = c.decision == DECISION_SCORE ? 1 : 0;
+    k.consec = 0;
+    k.dec_open = 0;
     bar();
 }
 
@@ -351,6 +357,9 @@ DEV void load_ctrl(Ctx& c, Ctl& k) {
     k.gate_fail = uni64(g.gate_fail);
     k.completes = uni64(g.completes);
     k.hash = (uint64_t)uni64((int64_t)g.hash);
+    k.use_score = uni(g.use_score);
+    k.consec = uni(g.consec);
+    k.dec_open = uni(g.dec_open);
     k.steps = 0;
     bar();
 }
@@ -395,6 +404,9 @@ DEV void save_ctrl(Ctx& c, const Ctl& k) {
     g.gate_fail = k.gate_fail;
     g.completes = k.completes;
     g.hash = k.hash;
+    g.use_score = k.use_score;
+    g.consec = k.consec;
+    g.dec_open = k.dec_open;
     bar();
 }
 
@@ -651,6 +663,16 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
         return;
     }
     k.conflicts += 1;
+    // learned Decision: a run of fallback_after conflicts with no decision
+    // reaching a conflict-free fixpoint hands Decision back to occurrences
+    k.dec_open = 0;
+    if (k.use_score) {
+        k.consec += 1;
+        if (c.fallback_after >= 0 && k.consec >= c.fallback_after) {
+            k.use_score = 0;
+            k.hash = fnv(k.hash, 7);
+        }
+    }
     int topl, bj, nN;
     if (sat) {
         topl = k.cdl;
@@ -774,15 +796,24 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
 // the highest occurrence count of the head wins, ties to the lowest rule;
 // T b_r is assigned at a new level.  Without a candidate,
 // CompleteAssignment falsifies every unassigned atom.
+// The search stands at a conflict-free fixpoint: if a decision led here,
+// the run of consecutive conflicts is over.
+DEV void at_fixpoint(Ctl& k) {
+    if (k.dec_open) k.consec = 0;
+}
+
 DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
     const int T = c.T, tid = c.tid, W = c.W, A = k.A, Rh = k.Rh;
+    at_fixpoint(k);
+    // key: head score (signed, biased to keep its order) then lowest rule
+    const int32_t* score = k.use_score ? c.RS : c.RO;
     unsigned long long best = 0ull;
     for (int j = tid; j < Rh; j += T) {
         int p = c.RH[j];
         if (vget(c.valb, p) != 0u) continue;
         int t = A + 3 * j + 2;
         if (vget(c.valb, t) != VT || vget(c.valb, t + 1) == VF) continue;
-        unsigned long long key = ((unsigned long long)(uint32_t)c.RO[j] << 32) |
+        unsigned long long key = ((unsigned long long)((uint32_t)score[j] ^ 0x80000000u) << 32) |
                                  (unsigned long long)(0xffffffffu - (uint32_t)j);
         best = key > best ? key : best;
     }
@@ -805,6 +836,7 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         k.qh = k.qt;
         k.qt = k.qt + 1;
         k.decisions += 1;
+        k.dec_open = 1;
         k.hash = fnv(k.hash, 1);
         k.hash = fnv(k.hash, j);
         return STEP_DECIDE;
@@ -841,6 +873,7 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
 // b_r is false in M.
 DEV void step_gate(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model) {
     const int T = c.T, tid = c.tid, W = c.W, A = k.A, Rh = k.Rh;
+    at_fixpoint(k);
     uint32_t* lm = c.pendb;   // 1 bit per atom; the pending map is idle here
     for (;;) {
         c.scr->changed = 0;
@@ -986,6 +1019,8 @@ __global__ __launch_bounds__(MAXT) void k_search(KArgs a) {
     Ctx c;
     Ctl k;
     c.W = a.W;
+    c.decision = a.decision;
+    c.fallback_after = a.fallback_after;
     c.T = MAXT;
     c.tid = threadIdx.x;
     c.lane = threadIdx.x & 63;

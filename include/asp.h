@@ -114,6 +114,9 @@ typedef struct {
                                   stream, with LDS sized for its largest
                                   instance (more classes: more resident
                                   workgroups) */
+    int32_t class_threads[4];  /* batches: threads per workgroup of class c
+                                  (c = 0 holds the largest instances); 0 takes
+                                  `threads` */
 } asp_schedule;
 
 /* Search counters (the paper's Fig. 1/2 metrics plus literal checks).
@@ -125,6 +128,9 @@ typedef struct {
     uint64_t trace_hash;       /* FNV-1a 64 over the decision/learning events */
     int32_t status;            /* final status of the instance */
     int32_t last_step;         /* ASP_STEP_* of the last step run */
+    int64_t ns_total;          /* device time of the solve (solve calls only) */
+    int64_t ns_round, ns_learn, ns_decide, ns_gate;  /* split by step kind;
+                                  ns_decide includes CompleteAssignment */
 } asp_stats;
 
 typedef struct {
@@ -287,6 +293,14 @@ int32_t asp_batch_results(asp_batch *batch, void *stream, int32_t *verdicts,
 /* Device time of the last asp_solve_batch, in milliseconds, between HIP
  * events recorded on the caller's stream around the forked launches. */
 int32_t asp_batch_last_ms(asp_batch *batch, double *ms);
+
+/* The launches of the batch: *n_classes launches; launch c solves instances
+ * order[first[c] .. first[c]+count[c]) with threads[c] threads per
+ * workgroup, and took ms[c] milliseconds in the last asp_solve_batch (HIP
+ * events on its stream; 0 before any solve).  Arrays of 4 entries (order:
+ * n entries); any pointer may be NULL. */
+int32_t asp_batch_launch_info(asp_batch *batch, int32_t *n_classes, int32_t *first,
+                              int32_t *count, int32_t *threads, double *ms, int32_t *order);
 
 int32_t asp_batch_free(asp_batch *batch);
 

@@ -40,7 +40,8 @@ class asp_limits(C.Structure):
 
 
 class asp_schedule(C.Structure):
-    _fields_ = [("threads", C.c_int32), ("classes", C.c_int32)]
+    _fields_ = [("threads", C.c_int32), ("classes", C.c_int32),
+                ("class_threads", C.c_int32 * 4)]
 
 
 _STAT_NAMES = ("rounds", "visits", "literal_checks", "propagations", "decisions", "conflicts",
@@ -49,7 +50,8 @@ _STAT_NAMES = ("rounds", "visits", "literal_checks", "propagations", "decisions"
 
 class asp_stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in _STAT_NAMES] + [
-        ("trace_hash", C.c_uint64), ("status", C.c_int32), ("last_step", C.c_int32)]
+        ("trace_hash", C.c_uint64), ("status", C.c_int32), ("last_step", C.c_int32)] + [
+        (n, C.c_int64) for n in ("ns_total", "ns_round", "ns_learn", "ns_decide", "ns_gate")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -128,7 +130,7 @@ EXPORTS = (
     "asp_status_str", "asp_last_error", "asp_set_scores", "asp_get_scores",
     "asp_batch_set_scores", "asp_batch_get_scores", "asp_scorer_workspace",
     "asp_batch_scorer_workspace", "asp_score_program", "asp_score_batch",
-    "asp_batch_train_readout",
+    "asp_batch_train_readout", "asp_batch_launch_info",
 )
 
 _lib = None
@@ -161,6 +163,7 @@ def lib():
             "asp_solve_batch": (i32, [P, P, C.POINTER(asp_limits)]),
             "asp_batch_results": (i32, [P, P, P, P, P]),
             "asp_batch_last_ms": (i32, [P, C.POINTER(C.c_double)]),
+            "asp_batch_launch_info": (i32, [P, C.POINTER(i32), P, P, P, P, P]),
             "asp_batch_free": (i32, [P]),
             "asp_status_str": (C.c_char_p, [i32]),
             "asp_last_error": (i32, [C.c_char_p, u64]),
@@ -288,7 +291,7 @@ class Program:
         """Allocate the arena (torch) and upload the program."""
         self.arena = _arena(self.sizes.device_bytes, device)
         self.stream = stream
-        sch = asp_schedule(int(threads), 1)
+        sch = asp_schedule(int(threads), 1, (C.c_int32 * 4)(0, 0, 0, 0))
         _check(lib().asp_bind_device(self._h, C.c_void_p(self.arena.data_ptr()),
                                      int(self.arena.numel()), _stream_ptr(stream), C.byref(sch)))
         return self
@@ -390,11 +393,12 @@ class Batch:
     """Many programs solved together (asp_solve_batch): one workgroup per
     program, one launch per LDS size class."""
 
-    def __init__(self, programs, threads: int = 128, classes: int = 4):
+    def __init__(self, programs, threads: int = 128, classes: int = 4, class_threads=None):
         self.programs = list(programs)
         arr = (C.c_void_p * len(self.programs))(*[p._h.value for p in self.programs])
         self._arr = arr
-        sch = asp_schedule(int(threads), int(classes))
+        ct = list(class_threads or []) + [0] * 4
+        sch = asp_schedule(int(threads), int(classes), (C.c_int32 * 4)(*[int(x) for x in ct[:4]]))
         h = C.c_void_p()
         nb, mb = C.c_uint64(0), C.c_uint64(0)
         _check(lib().asp_batch_create(len(self.programs), C.cast(arr, C.c_void_p), C.byref(sch),
@@ -466,6 +470,15 @@ class Batch:
         """Enqueue the batched solve on the stream (asynchronous)."""
         _check(lib().asp_solve_batch(self._h, _stream_ptr(self.stream),
                                      C.byref(lim) if lim else None))
+
+    def launch_info(self):
+        """[(first, count, threads, ms)] per launch class, and the instance order."""
+        n = C.c_int32(0)
+        first, count, thr = (C.c_int32 * 4)(), (C.c_int32 * 4)(), (C.c_int32 * 4)()
+        ms = (C.c_double * 4)()
+        order = np.zeros(len(self.programs), np.int32)
+        _check(lib().asp_batch_launch_info(self._h, C.byref(n), first, count, thr, ms, _ptr(order)))
+        return [(first[c], count[c], thr[c], ms[c]) for c in range(n.value)], order
 
     def last_ms(self) -> float:
         ms = C.c_double(0)

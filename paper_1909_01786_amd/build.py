@@ -33,7 +33,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") or src == "api.cpp" else []
+        lang = ["-x", "hip"] if src.endswith(".hip") or src in ("api.cpp", "encode.cpp") else []
         cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

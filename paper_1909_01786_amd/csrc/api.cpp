@@ -47,6 +47,8 @@ int32_t fail(int32_t code, const std::string& msg) {
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+int g_clock_khz = 0;   // device wall-clock rate (kHz), set by device_info()
+
 struct DeviceInfo {
     int ok = 0;
     int cus = 0;
@@ -65,6 +67,7 @@ DeviceInfo device_info() {
     int rate = 0;
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) == hipSuccess)
         d.clock_khz = rate;
+    g_clock_khz = d.clock_khz;
     d.ok = d.cus > 0;
     return d;
 }
@@ -77,7 +80,7 @@ bool valid_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 |
 // One launch of the search kernel: instances order[first .. first+count),
 // LDS sized for the largest of them.
 struct LaunchClass {
-    int32_t first = 0, count = 0, words = 1;
+    int32_t first = 0, count = 0, words = 1, threads = 128;
     size_t lds = 0;
 };
 
@@ -137,7 +140,7 @@ struct asp_batch {
     uint8_t* arena = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_fork = nullptr;
     std::vector<hipStream_t> streams;    // one per launch class (default priority)
-    std::vector<hipEvent_t> ev_join;
+    std::vector<hipEvent_t> ev_start, ev_join;  // per launch class (timed)
     bool timed = false;
 };
 
@@ -170,7 +173,8 @@ std::vector<int64_t> class_bounds(int32_t classes) {
 }
 
 int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_options& opt,
-                  int32_t threads, int32_t n_classes, Plan& P) {
+                  int32_t threads, int32_t n_classes, Plan& P,
+                  const int32_t* class_threads = nullptr) {
     P = Plan();
     P.n = (int32_t)progs.size();
     P.threads = threads;
@@ -207,7 +211,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
         P.tot_ngo += (int64_t)h.ng_off.size();
         P.tot_ngl += (int64_t)h.ng_lits.size();
         P.tot_mo += (int64_t)h.map_off.size();
-        P.tot_mi += (int64_t)h.map_ids.size();
+        P.tot_mi += (int64_t)h.map_ent.size();
         P.tot_rules += (int64_t)h.rule_head.size();
         P.tot_rbo += (int64_t)h.rb_off.size();
         P.tot_rbl += (int64_t)h.rb_lits.size();
@@ -241,7 +245,9 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
         while (k < P.n && cls(P.order[k]) == c) vmax = std::max<int64_t>(vmax, progs[P.order[k++]]->V);
         lc.count = k - lc.first;
         lc.words = (int32_t)((vmax + 1 + 15) / 16);
-        lc.lds = lds_bytes(threads, lc.words);
+        const int ci = (int)P.classes.size();
+        lc.threads = (class_threads && ci < 4 && class_threads[ci] > 0) ? class_threads[ci] : threads;
+        lc.lds = lds_bytes(lc.threads, lc.words);
         P.classes.push_back(lc);
     }
     uint64_t o = 0;
@@ -256,7 +262,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.off_ngo = take(4 * (uint64_t)P.tot_ngo);
     P.off_ngl = take(4 * (uint64_t)P.tot_ngl);
     P.off_mo = take(4 * (uint64_t)P.tot_mo);
-    P.off_mi = take(4 * (uint64_t)P.tot_mi);
+    P.off_mi = take(sizeof(MapEntry) * (uint64_t)P.tot_mi);
     P.off_rh = take(4 * (uint64_t)P.tot_rules);
     P.off_ro = take(4 * (uint64_t)P.tot_rules);
     P.off_rbo = take(4 * (uint64_t)P.tot_rbo);
@@ -291,7 +297,7 @@ int32_t upload_static(const std::vector<const HostProgram*>& progs, const Plan& 
     std::vector<int32_t> ngo = concat(progs, &HostProgram::ng_off);
     std::vector<int32_t> ngl = concat(progs, &HostProgram::ng_lits);
     std::vector<int32_t> mo = concat(progs, &HostProgram::map_off);
-    std::vector<int32_t> mi = concat(progs, &HostProgram::map_ids);
+    std::vector<MapEntry> mi = concat(progs, &HostProgram::map_ent);
     std::vector<int32_t> rh = concat(progs, &HostProgram::rule_head);
     std::vector<int32_t> ro = concat(progs, &HostProgram::rule_occ);
     std::vector<int32_t> rbo = concat(progs, &HostProgram::rb_off);
@@ -302,7 +308,7 @@ int32_t upload_static(const std::vector<const HostProgram*>& progs, const Plan& 
     HIPCHK(put(P.off_ngo, ngo.data(), 4 * ngo.size()));
     HIPCHK(put(P.off_ngl, ngl.data(), 4 * ngl.size()));
     HIPCHK(put(P.off_mo, mo.data(), 4 * mo.size()));
-    HIPCHK(put(P.off_mi, mi.data(), 4 * mi.size()));
+    HIPCHK(put(P.off_mi, mi.data(), sizeof(MapEntry) * mi.size()));
     HIPCHK(put(P.off_rh, rh.data(), 4 * rh.size()));
     HIPCHK(put(P.off_ro, ro.data(), 4 * ro.size()));
     HIPCHK(put(P.off_rbo, rbo.data(), 4 * rbo.size()));
@@ -321,7 +327,7 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& 
     a.ng_off = (const int32_t*)(arena + P.off_ngo);
     a.ng_lits = (const int32_t*)(arena + P.off_ngl);
     a.map_off = (const int32_t*)(arena + P.off_mo);
-    a.map_ids = (const int32_t*)(arena + P.off_mi);
+    a.map_ent = (const MapEntry*)(arena + P.off_mi);
     a.rule_head = (const int32_t*)(arena + P.off_rh);
     a.rule_occ = (const int32_t*)(arena + P.off_ro);
     a.rule_score = (const int32_t*)(arena + P.off_rs);
@@ -357,6 +363,11 @@ void apply_limits(KArgs& a, const Plan& P, const asp_limits* lim, const DeviceIn
         a.max_steps = -1;
 }
 
+
+int64_t ticks_ns(uint64_t t) {
+    return g_clock_khz > 0 ? (int64_t)((double)t * 1e6 / (double)g_clock_khz) : 0;
+}
+
 void to_stats(const DevStats& d, asp_stats* s) {
     s->rounds = d.rounds;
     s->visits = d.visits;
@@ -371,6 +382,11 @@ void to_stats(const DevStats& d, asp_stats* s) {
     s->trace_hash = d.hash;
     s->status = d.status;
     s->last_step = d.last_step;
+    s->ns_total = ticks_ns(d.t_total);
+    s->ns_round = ticks_ns(d.t_round);
+    s->ns_learn = ticks_ns(d.t_learn);
+    s->ns_decide = ticks_ns(d.t_decide);
+    s->ns_gate = ticks_ns(d.t_gate);
 }
 
 void ctrl_stats(const SlotCtrl& k, asp_stats* s) {
@@ -387,6 +403,7 @@ void ctrl_stats(const SlotCtrl& k, asp_stats* s) {
     s->trace_hash = k.hash;
     s->status = k.status;
     s->last_step = k.last_step;
+    s->ns_total = s->ns_round = s->ns_learn = s->ns_decide = s->ns_gate = 0;
 }
 
 int32_t check_launch(const Plan& P, const DeviceInfo& di) {
@@ -395,7 +412,8 @@ int32_t check_launch(const Plan& P, const DeviceInfo& di) {
         return fail(ASP_E_CAPACITY, "largest instance needs " + std::to_string(P.max_lds()) +
                                         " bytes of LDS, device allows " +
                                         std::to_string(di.max_lds));
-    (void)set_max_lds(P.threads, P.max_lds());  // best effort: older runtimes ignore it
+    for (const LaunchClass& c : P.classes)
+        (void)set_max_lds(c.threads, c.lds);  // best effort: older runtimes ignore it
     return ASP_OK;
 }
 
@@ -410,7 +428,7 @@ int32_t run_single(asp_program* p, hipStream_t s, int32_t mode, int32_t mask, in
     apply_limits(a, p->plan, lim, di);
     a.step_mask = mask;
     a.max_steps = steps;
-    HIPCHK(launch_search(a, p->threads, 1, lc.lds, s));
+    HIPCHK(launch_search(a, lc.threads, 1, lc.lds, s));
     HIPCHK(hipStreamSynchronize(s));
     return ASP_OK;
 }
@@ -581,7 +599,7 @@ ScorerArgs scorer_args(const std::vector<const HostProgram*>& progs, const Plan&
     a.ng_off = (const int32_t*)(arena + P.off_ngo);
     a.ng_lits = (const int32_t*)(arena + P.off_ngl);
     a.map_off = (const int32_t*)(arena + P.off_mo);
-    a.map_ids = (const int32_t*)(arena + P.off_mi);
+    a.map_ent = (const MapEntry*)(arena + P.off_mi);
     a.rule_head = (const int32_t*)(arena + P.off_rh);
     a.w = ws + S.off_w;
     a.hv_off = (const int64_t*)(ws + S.off_hvo);
@@ -828,7 +846,7 @@ int32_t asp_solve(asp_program* p, void* stream, const asp_limits* lim, uint8_t* 
     const LaunchClass& lc = p->plan.classes[0];
     KArgs a = make_args(p->plan, p->arena, MODE_SOLVE, lc);
     apply_limits(a, p->plan, lim, di);
-    HIPCHK(launch_search(a, p->threads, 1, lc.lds, s));
+    HIPCHK(launch_search(a, lc.threads, 1, lc.lds, s));
     DevStats d;
     int32_t verdict = 0;
     HIPCHK(hipMemcpyAsync(&d, a.stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
@@ -994,7 +1012,7 @@ int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
     k.hash = st->stats.trace_hash;
     std::vector<int32_t> dec(Rh + 3, 0);
     for (int32_t l = 2; l <= cdl; ++l) dec[l] = st->dec[l];
-    std::vector<int32_t> win(V + 1, 0x7fffffff);
+    std::vector<uint64_t> win(V + 1, ~0ull);
     std::vector<int32_t> lvl(st->lvl, st->lvl + V + 1);
     hipStream_t s = (hipStream_t)stream;
     const SlotLayout L = slot0(p);
@@ -1007,7 +1025,7 @@ int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
     HIPCHK(put(L.val8, st->val, (size_t)V + 1));
     HIPCHK(put(L.lvl, lvl.data(), 4 * lvl.size()));
     HIPCHK(put(L.deps, st->deps, 8 * ((size_t)V + 1) * W));
-    HIPCHK(put(L.win, win.data(), 4 * win.size()));
+    HIPCHK(put(L.win, win.data(), 8 * win.size()));
     HIPCHK(put(L.trail, trail.data(), 4 * trail.size()));
     HIPCHK(put(L.tlim, tlim.data(), 4 * tlim.size()));
     HIPCHK(put(L.dec, dec.data(), 4 * dec.size()));
@@ -1030,6 +1048,11 @@ int32_t asp_batch_create(int32_t n, asp_program* const* progs, const asp_schedul
     int32_t classes = sched ? sched->classes : 4;
     if (!valid_threads(threads) || classes < 1 || classes > 4)
         return fail(ASP_E_INVALID, "bad schedule");
+    int32_t cth[4] = {0, 0, 0, 0};
+    for (int c = 0; sched && c < 4; ++c) {
+        cth[c] = sched->class_threads[c];
+        if (cth[c] != 0 && !valid_threads(cth[c])) return fail(ASP_E_INVALID, "bad class threads");
+    }
     std::unique_ptr<asp_batch> b(new asp_batch());
     b->opt = progs[0] ? progs[0]->opt : default_options();
     for (int32_t i = 0; i < n; ++i) {
@@ -1041,7 +1064,7 @@ int32_t asp_batch_create(int32_t n, asp_program* const* progs, const asp_schedul
             return fail(ASP_E_INVALID, "batch programs must share their options");
         b->progs.push_back(&progs[i]->hp);
     }
-    int32_t rc = make_plan(b->progs, b->opt, threads, classes, b->plan);
+    int32_t rc = make_plan(b->progs, b->opt, threads, classes, b->plan, cth);
     if (rc) return rc;
     if (device_bytes) *device_bytes = b->plan.total;
     if (model_bytes) *model_bytes = (uint64_t)b->plan.tot_model;
@@ -1155,19 +1178,26 @@ int32_t asp_solve_batch(asp_batch* b, void* stream, const asp_limits* lim) {
         HIPCHK(hipEventCreate(&b->ev1));
         HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     }
+    while (b->ev_join.size() < nc) {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        b->ev_start.push_back(e0);
+        b->ev_join.push_back(e1);
+    }
     while (nc > 1 && b->streams.size() < nc) {
         hipStream_t t;
-        hipEvent_t e;
         HIPCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
-        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         b->streams.push_back(t);
-        b->ev_join.push_back(e);
     }
     HIPCHK(hipEventRecord(b->ev0, s));
     if (nc == 1) {
-        KArgs a = make_args(b->plan, b->arena, MODE_SOLVE, b->plan.classes[0]);
+        const LaunchClass& lc = b->plan.classes[0];
+        KArgs a = make_args(b->plan, b->arena, MODE_SOLVE, lc);
         apply_limits(a, b->plan, lim, di);
-        HIPCHK(launch_search(a, b->plan.threads, b->plan.classes[0].count, b->plan.classes[0].lds, s));
+        HIPCHK(hipEventRecord(b->ev_start[0], s));
+        HIPCHK(launch_search(a, lc.threads, lc.count, lc.lds, s));
+        HIPCHK(hipEventRecord(b->ev_join[0], s));
     } else {
         // fork: every class launches on its own stream once the caller's
         // stream has reached this point; join back before ev1
@@ -1177,7 +1207,8 @@ int32_t asp_solve_batch(asp_batch* b, void* stream, const asp_limits* lim) {
             KArgs a = make_args(b->plan, b->arena, MODE_SOLVE, lc);
             apply_limits(a, b->plan, lim, di);
             HIPCHK(hipStreamWaitEvent(b->streams[c], b->ev_fork, 0));
-            HIPCHK(launch_search(a, b->plan.threads, lc.count, lc.lds, b->streams[c]));
+            HIPCHK(hipEventRecord(b->ev_start[c], b->streams[c]));
+            HIPCHK(launch_search(a, lc.threads, lc.count, lc.lds, b->streams[c]));
             HIPCHK(hipEventRecord(b->ev_join[c], b->streams[c]));
         }
         for (size_t c = 0; c < nc; ++c) HIPCHK(hipStreamWaitEvent(s, b->ev_join[c], 0));
@@ -1219,12 +1250,37 @@ int32_t asp_batch_last_ms(asp_batch* b, double* ms) {
     return ASP_OK;
 }
 
+int32_t asp_batch_launch_info(asp_batch* b, int32_t* n_classes, int32_t* first, int32_t* count,
+                              int32_t* threads, double* ms, int32_t* order) {
+    if (!b) return fail(ASP_E_INVALID, "null batch");
+    const Plan& P = b->plan;
+    const int nc = (int)P.classes.size();
+    if (n_classes) *n_classes = nc;
+    for (int c = 0; c < nc; ++c) {
+        if (first) first[c] = P.classes[c].first;
+        if (count) count[c] = P.classes[c].count;
+        if (threads) threads[c] = P.classes[c].threads;
+        if (ms) {
+            ms[c] = 0.0;
+            if (b->timed && c < (int)b->ev_join.size()) {
+                HIPCHK(hipEventSynchronize(b->ev_join[c]));
+                float f = 0.f;
+                HIPCHK(hipEventElapsedTime(&f, b->ev_start[c], b->ev_join[c]));
+                ms[c] = (double)f;
+            }
+        }
+    }
+    if (order) memcpy(order, P.order.data(), 4 * P.order.size());
+    return ASP_OK;
+}
+
 int32_t asp_batch_free(asp_batch* b) {
     if (b) {
         if (b->ev0) (void)hipEventDestroy(b->ev0);
         if (b->ev1) (void)hipEventDestroy(b->ev1);
         if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
         for (hipEvent_t e : b->ev_join) (void)hipEventDestroy(e);
+        for (hipEvent_t e : b->ev_start) (void)hipEventDestroy(e);
         for (hipStream_t t : b->streams) (void)hipStreamDestroy(t);
         delete b;
     }

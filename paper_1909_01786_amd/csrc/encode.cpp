@@ -167,12 +167,23 @@ int encode_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
     P->map_off.assign(NL + 1, 0);
     for (int32_t l : P->ng_lits) P->map_off[lit_index(l) + 1] += 1;
     for (int64_t i = 0; i < NL; ++i) P->map_off[i + 1] += P->map_off[i];
-    P->map_ids.resize(P->ng_lits.size());
+    P->map_ent.resize(P->ng_lits.size());
     {
         std::vector<int32_t> fill(P->map_off.begin(), P->map_off.end() - 1);
-        for (int64_t id = 0; id < G; ++id)
-            for (int32_t k = P->ng_off[id]; k < P->ng_off[id + 1]; ++k)
-                P->map_ids[fill[lit_index(P->ng_lits[k])]++] = (int32_t)id;
+        for (int64_t id = 0; id < G; ++id) {
+            const int32_t b = P->ng_off[id], e = P->ng_off[id + 1];
+            for (int32_t k = b; k < e; ++k) {
+                MapEntry m{(int32_t)id, P->ng_lits[k], 0, 0};
+                if (e - b > 3) {
+                    m.o1 = kLongNogood;
+                } else {
+                    int32_t* o = &m.o1;
+                    for (int32_t q = b; q < e; ++q)
+                        if (q != k) *o++ = P->ng_lits[q];
+                }
+                P->map_ent[fill[lit_index(P->ng_lits[k])]++] = m;
+            }
+        }
     }
 
     // occurrence count of each atom over Delta_0 (an atom occurs at most

@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include "layout.h"
+
 namespace asp {
 
 // A ground program turned into the data the device search reads.
@@ -15,7 +17,7 @@ struct HostProgram {
     std::vector<int32_t> ng_off;         // Delta_0 CSR offsets (n+1)
     std::vector<int32_t> ng_lits;
     std::vector<int32_t> map_off;        // 2(V+1)+1
-    std::vector<int32_t> map_ids;
+    std::vector<MapEntry> map_ent;       // literal -> nogood entries, ids ascending
     std::vector<int32_t> rule_head;      // per headed rule
     std::vector<int32_t> rule_occ;       // occurrence count of the head in Delta_0
     std::vector<int32_t> rb_off;         // per headed rule body (deduplicated)

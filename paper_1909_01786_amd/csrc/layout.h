@@ -18,12 +18,21 @@ namespace asp {
 constexpr int kMaxW = 64;           // Deps words per variable
 constexpr int kAlign = 256;
 
+// One entry of the literal -> nogood map: the nogood's id, the map's own
+// literal, and the nogood's other literals when it has at most three (0
+// pads the unused ones).  A longer nogood has o1 = kLongNogood and is read
+// from the nogood CSR.  A visit of a short nogood is one 16-byte load.
+struct alignas(16) MapEntry {
+    int32_t id, self, o1, o2;
+};
+constexpr int32_t kLongNogood = (int32_t)0x80000000;
+
 // Static description of one instance (element offsets into the packed arrays).
 struct InstDesc {
     int64_t ng_off;    // into ng_off[]: n_static+1 entries, values relative to ng_lits
     int64_t ng_lits;   // into ng_lits[]
     int64_t map_off;   // into map_off[]: 2(V+1)+1 entries, values relative to map_ids
-    int64_t map_ids;   // into map_ids[]
+    int64_t map_ids;   // into map_ent[]
     int64_t rules;     // into rule_head[] / rule_occ[] (Rh entries)
     int64_t rb_off;    // into rb_off[] (Rh+1 entries, values relative to rb_lits)
     int64_t rb_lits;   // into rb_lits[] (rule bodies, +a body+ / -a body-)
@@ -55,7 +64,7 @@ struct SlotLayout {
     int64_t val8;       // int8[V+1]
     int64_t lvl;        // int32[V+1]
     int64_t deps;       // uint64[(V+1)*W]
-    int64_t win;        // int32[V+1]
+    int64_t win;        // uint64[V+1] winner key: (id*2 + pol) << 32 | map entry
     int64_t trail;      // int32[V+1]
     int64_t tlim;       // int32[Rh+3]
     int64_t dec;        // int32[Rh+3]
@@ -82,7 +91,7 @@ __host__ __device__ inline SlotLayout slot_layout(int64_t V, int64_t Rh, int32_t
     ASP_TAKE(val8, V1);
     ASP_TAKE(lvl, 4 * V1);
     ASP_TAKE(deps, 8 * V1 * W);
-    ASP_TAKE(win, 4 * V1);
+    ASP_TAKE(win, 8 * V1);
     ASP_TAKE(trail, 4 * V1);
     ASP_TAKE(tlim, 4 * R3);
     ASP_TAKE(dec, 4 * R3);
@@ -103,6 +112,7 @@ struct DevStats {
             gate_fail, completes;
     uint64_t hash;
     int32_t status, last_step;
+    uint64_t t_total, t_round, t_learn, t_decide, t_gate;   // wall-clock ticks
 };
 
 enum StepKind : int32_t {
@@ -133,7 +143,7 @@ struct KArgs {
     const int32_t* ng_off;
     const int32_t* ng_lits;
     const int32_t* map_off;
-    const int32_t* map_ids;
+    const MapEntry* map_ent;
     const int32_t* rule_head;
     const int32_t* rule_occ;
     const int32_t* rule_score;   // score of each rule's head (score-driven Decision)

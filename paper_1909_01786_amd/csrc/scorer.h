@@ -14,7 +14,8 @@ struct ScorerTile {
 
 struct ScorerArgs {
     const InstDesc* inst;
-    const int32_t *ng_off, *ng_lits, *map_off, *map_ids, *rule_head;
+    const int32_t *ng_off, *ng_lits, *map_off, *rule_head;
+    const MapEntry* map_ent;
     const uint8_t* w;            // device copy of asp_scorer_weights
     const int64_t* hv_off;       // per instance: byte offset of its (V+1) x 64 codes
     const int64_t* hc_off;       // per instance: byte offset of its n_static x 64 codes

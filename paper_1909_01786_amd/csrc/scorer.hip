@@ -313,7 +313,7 @@ __global__ __launch_bounds__(NT) void k_vars(ScorerArgs a, int l, int last) {
         const InstDesc& d = a.inst[tl.inst];
         const int rows = min(TR, d.V + 1 - tl.row0);
         const int32_t* MO = a.map_off + d.map_off + 2 * tl.row0;
-        const int32_t* MI = a.map_ids + d.map_ids;
+        const MapEntry* ME = a.map_ent + d.map_ids;
         const uint8_t* hc = a.ws + a.hc_off[tl.inst];
         uint8_t* hv = a.ws + a.hv_off[tl.inst] + (size_t)tl.row0 * H;
         const int nseg = 2 * rows;
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(NT) void k_vars(ScorerArgs a, int l, int last) {
         for (int eb = e0; eb < e1; eb += TR) {
             const int ne = min(TR, e1 - eb);
             if (er < ne) {
-                const int c = MI[eb + er];
+                const int c = ME[eb + er].id;
                 load_codes16(L.opa + er * LD + part * 16, hc + (size_t)c * H + part * 16);
                 if (part == 0) {
                     int lo = 0, hi = nseg - 1;

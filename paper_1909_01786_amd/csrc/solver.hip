@@ -43,7 +43,8 @@ namespace asp {
 #define DEV __device__ __forceinline__
 
 constexpr uint32_t VT = 1u, VF = 2u;          // 2-bit value codes
-constexpr int32_t WIN_NONE = 0x7fffffff;
+constexpr unsigned long long WIN_NONE = ~0ull;   // no implier this round
+constexpr uint32_t NO_ENTRY = 0xffffffffu;      // implier without a map entry (learned)
 constexpr uint64_t FNV_BASIS = 1469598103934665603ull;
 constexpr uint64_t FNV_PRIME = 1099511628211ull;
 constexpr int kMaxWaves = 16;
@@ -56,6 +57,9 @@ struct Ctl {
     int64_t learned_lits, rounds, props, decisions, conflicts, learned, learned_len, gate_fail,
             completes, steps, visits, checks;
     uint64_t hash;
+    // device time per step kind (wall-clock ticks; read per wave, so the
+    // copies of different waves may differ -- timing only, never control)
+    uint64_t t_round, t_learn, t_decide, t_gate;
 };
 
 // LDS words through which lanes exchange per-phase results.
@@ -69,11 +73,13 @@ struct Scr {
 
 struct Ctx {
     // per-instance static arrays
-    const int32_t *NO, *NL, *MO, *MI, *RH, *RO, *RS, *RBO, *RBL;
+    const int32_t *NO, *NL, *MO, *RH, *RO, *RS, *RBO, *RBL;
+    const MapEntry* ME;
     // per-slot arrays
     SlotCtrl* ctrl;
     int8_t* val8;
-    int32_t *lvl, *win, *trail, *tlim, *dec, *lptr, *ln, *lcap, *loff, *llits, *pool;
+    int32_t *lvl, *trail, *tlim, *dec, *lptr, *ln, *lcap, *loff, *llits, *pool;
+    unsigned long long* win;
     uint64_t* deps;
     int64_t pool_cap;
     // LDS
@@ -104,13 +110,13 @@ DEV int lidx(int l) { return 2 * lvar(l) + (l < 0 ? 1 : 0); }
 
 // The lowest-id implier per variable is shared only inside the workgroup:
 // workgroup-scope atomics, ordered by the barriers' workgroup fences.
-DEV int32_t ld_wg(const int32_t* p) {
+DEV unsigned long long ld_wg(const unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-DEV void st_wg(int32_t* p, int32_t v) {
+DEV void st_wg(unsigned long long* p, unsigned long long v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-DEV void min_wg(int32_t* p, int32_t v) {
+DEV void min_wg(unsigned long long* p, unsigned long long v) {
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -253,7 +259,7 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     c.NO = a.ng_off + d.ng_off;
     c.NL = a.ng_lits + d.ng_lits;
     c.MO = a.map_off + d.map_off;
-    c.MI = a.map_ids + d.map_ids;
+    c.ME = a.map_ent + d.map_ids;
     c.RH = a.rule_head + d.rules;
     c.RO = a.rule_occ + d.rules;
     c.RS = a.rule_score + d.rules;
@@ -263,7 +269,7 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     c.val8 = (int8_t*)(slot + lay.val8);
     c.lvl = (int32_t*)(slot + lay.lvl);
     c.deps = (uint64_t*)(slot + lay.deps);
-    c.win = (int32_t*)(slot + lay.win);
+    c.win = (unsigned long long*)(slot + lay.win);
     c.trail = (int32_t*)(slot + lay.trail);
     c.tlim = (int32_t*)(slot + lay.tlim);
     c.dec = (int32_t*)(slot + lay.dec);
@@ -315,6 +321,7 @@ DEV void reset_search(Ctx& c, Ctl& k) {
     k.use_score = c.decision == DECISION_SCORE ? 1 : 0;
     k.consec = 0;
     k.dec_open = 0;
+    k.t_round = k.t_learn = k.t_decide = k.t_gate = 0;
     bar();
 }
 
@@ -361,6 +368,7 @@ DEV void load_ctrl(Ctx& c, Ctl& k) {
     k.consec = uni(g.consec);
     k.dec_open = uni(g.dec_open);
     k.steps = 0;
+    k.t_round = k.t_learn = k.t_decide = k.t_gate = 0;
     bar();
 }
 
@@ -458,27 +466,50 @@ DEV void step_init(Ctx& c, Ctl& k) {
     }
 }
 
-// Classification of one visited nogood against the round's snapshot.
-// pass 0: record violations and unit implications; pass 1: conflicts of
-// unit nogoods that lost their variable to a lower-id implier of the
-// other value.
-DEV void visit_one(Ctx& c, const Ctl& k, int id, int pass) {
-    const int32_t* lits;
-    int len;
-    ng_span(c, k, id, lits, len);
-    if (pass == 0) {
-        c.my_visits += 1ull;
-        c.my_checks += (unsigned long long)len;
-    }
-    int open = 0, u = 0;
-    for (int q = 0; q < len; ++q) {
-        int l = lits[q];
-        uint32_t s = vget(c.valb, lvar(l));
-        if (s == 0u) {
-            if (++open > 1) return;
-            u = l;
-        } else if (s != lcode(l)) {
-            return;  // satisfied
+// Classification of one visited nogood against the round's snapshot.  A
+// short static nogood comes with its map entry, whose other literals are
+// all that must be read (the map's own literal is true in the snapshot);
+// any other nogood is read through the nogood arrays.
+// pass 0: record violations and unit implications (winner key: id and
+// implied value, then the map entry the Deps will be read from); pass 1:
+// conflicts of unit nogoods that lost their variable to a lower-id implier
+// of the other value.
+DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eidx, int pass) {
+    int len, open = 0, u = 0;
+    if (e.o1 != kLongNogood) {
+        const int o1 = e.o1, o2 = e.o2;
+        len = 1 + (o1 != 0 ? 1 : 0) + (o2 != 0 ? 1 : 0);
+        if (pass == 0) {
+            c.my_visits += 1ull;
+            c.my_checks += (unsigned long long)len;
+        }
+        if (o1 != 0) {
+            const uint32_t s = vget(c.valb, lvar(o1));
+            if (s == 0u) { open = 1; u = o1; }
+            else if (s != lcode(o1)) return;   // satisfied
+        }
+        if (o2 != 0) {
+            const uint32_t s = vget(c.valb, lvar(o2));
+            if (s == 0u) { if (++open > 1) return; u = o2; }
+            else if (s != lcode(o2)) return;
+        }
+    } else {
+        eidx = NO_ENTRY;
+        const int32_t* lits;
+        ng_span(c, k, id, lits, len);
+        if (pass == 0) {
+            c.my_visits += 1ull;
+            c.my_checks += (unsigned long long)len;
+        }
+        for (int q = 0; q < len; ++q) {
+            const int l = lits[q];
+            const uint32_t s = vget(c.valb, lvar(l));
+            if (s == 0u) {
+                if (++open > 1) return;
+                u = l;
+            } else if (s != lcode(l)) {
+                return;  // satisfied
+            }
         }
     }
     if (open == 0) {
@@ -489,7 +520,8 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, int pass) {
     const int x = lvar(u);
     const uint32_t code = u > 0 ? VF : VT;   // implied value of x
     if (pass == 0) {
-        min_wg(&c.win[x], id * 2 + (code == VF ? 1 : 0));
+        const uint32_t hi = (uint32_t)(id * 2 + (code == VF ? 1 : 0));
+        min_wg(&c.win[x], ((unsigned long long)hi << 32) | eidx);
         uint32_t sh = (uint32_t)(x & 15) << 1;
         uint32_t old = atomicOr(&c.pendb[x >> 4], code << sh);
         uint32_t ob = (old >> sh) & 3u;
@@ -500,8 +532,8 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, int pass) {
             c.scr->clash = 1;
         }
     } else {
-        int key = ld_wg(&c.win[x]);
-        uint32_t wcode = (key & 1) ? VF : VT;
+        const unsigned long long key = ld_wg(&c.win[x]);
+        const uint32_t wcode = ((key >> 32) & 1ull) ? VF : VT;
         if (wcode != code)
             atomicMin(&c.scr->conf_key, ((unsigned long long)(uint32_t)len << 32) | (uint32_t)id);
     }
@@ -538,10 +570,16 @@ DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
                 int mid = (lo + hi + 1) >> 1;
                 if (c.sOff[mid] <= q) lo = mid; else hi = mid - 1;
             }
-            int j = q - c.sOff[lo];
-            int cnt = c.sCs[lo];
-            int id = j < cnt ? c.MI[c.sS0[lo] + j] : c.pool[c.sL0[lo] + (j - cnt)];
-            visit_one(c, k, id, pass);
+            const int j = q - c.sOff[lo];
+            const int cnt = c.sCs[lo];
+            if (j < cnt) {
+                const uint32_t eidx = (uint32_t)(c.sS0[lo] + j);
+                const MapEntry e = c.ME[eidx];
+                visit_one(c, k, e.id, e, eidx, pass);
+            } else {
+                const MapEntry none{0, 0, kLongNogood, 0};
+                visit_one(c, k, c.pool[c.sL0[lo] + (j - cnt)], none, NO_ENTRY, pass);
+            }
         }
         bar();
     }
@@ -565,13 +603,25 @@ DEV void step_round(Ctx& c, Ctl& k) {
     // apply every implication, its Deps being the OR of the Deps of the
     // other variables of the winning nogood (mk_dl_bitmap)
     for (int i = qt + tid; i < nt; i += T) {
-        int x = c.trail[i];
-        int key = ld_wg(&c.win[x]);
-        int id = key >> 1;
-        uint32_t code = (key & 1) ? VF : VT;
+        const int x = c.trail[i];
+        const unsigned long long key = ld_wg(&c.win[x]);
+        const int id = (int)(key >> 33);
+        const uint32_t code = ((key >> 32) & 1ull) ? VF : VT;
+        const uint32_t eidx = (uint32_t)key;
         const int32_t* lits;
         int len;
-        ng_span(c, k, id, lits, len);
+        int32_t inl[3];
+        if (eidx != NO_ENTRY) {
+            // the winner is a short static nogood: its literals are in the entry
+            const MapEntry e = c.ME[eidx];
+            inl[0] = e.self;
+            inl[1] = e.o1;
+            inl[2] = e.o2;
+            lits = inl;
+            len = 1 + (e.o1 != 0 ? 1 : 0) + (e.o2 != 0 ? 1 : 0);
+        } else {
+            ng_span(c, k, id, lits, len);
+        }
         uint64_t* dx = c.deps + (size_t)x * W;
         if (W == 1) {
             unsigned long long acc = 0ull;
@@ -976,6 +1026,7 @@ DEV void run_search(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model, uint64_t t0)
         }
         kind = uni(kind);
         if (kind == STEP_DONE) break;
+        const uint64_t ts = wall_clock64();
         switch (kind) {
         case STEP_INIT: step_init(c, k); break;
         case STEP_ROUND: step_round(c, k); break;
@@ -983,6 +1034,11 @@ DEV void run_search(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model, uint64_t t0)
         case STEP_GATE: step_gate(c, k, a, model); break;
         default: kind = step_decide_or_complete(c, k); break;
         }
+        const uint64_t dt = wall_clock64() - ts;
+        if (kind == STEP_ROUND || kind == STEP_INIT) k.t_round += dt;
+        else if (kind == STEP_LEARN) k.t_learn += dt;
+        else if (kind == STEP_GATE) k.t_gate += dt;
+        else k.t_decide += dt;
         k.steps += 1;
         k.last_step = kind;
         if (k.status == ST_SAT) k.hash = fnv(k.hash, 4);
@@ -993,8 +1049,13 @@ DEV void run_search(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model, uint64_t t0)
 }
 
 // Every lane stores the same result values (identical stores).
-DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a) {
+DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a, uint64_t t0) {
     DevStats& d = a.stats[k.inst];
+    d.t_total = wall_clock64() - t0;
+    d.t_round = k.t_round;
+    d.t_learn = k.t_learn;
+    d.t_decide = k.t_decide;
+    d.t_gate = k.t_gate;
     d.rounds = k.rounds;
     d.visits = k.visits;
     d.checks = k.checks;
@@ -1048,7 +1109,7 @@ __global__ __launch_bounds__(MAXT) void k_search(KArgs a) {
         reset_search(c, k);
         run_search(c, k, a, a.models + a.inst[inst].model, t0);
         flush_counters(c, k);
-        write_result(c, k, a);
+        write_result(c, k, a, t0);
         save_ctrl(c, k);
     } else {
         bind_instance(c, k, a, 0);

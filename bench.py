@@ -235,7 +235,7 @@ def main():
     ap.add_argument("--W", type=int, default=1)
     ap.add_argument("--threads", type=int, default=128)
     ap.add_argument("--classes", type=int, default=4, help="LDS size classes (launches)")
-    ap.add_argument("--class-threads", default="", help="threads per class, largest first")
+    ap.add_argument("--class-threads", default="256,128,128,128", help="threads per class, largest first")
     ap.add_argument("--cap-ng", type=int, default=4096)
     ap.add_argument("--cap-lits", type=int, default=1 << 18)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -48,12 +48,19 @@ constexpr uint32_t NO_ENTRY = 0xffffffffu;      // implier without a map entry (
 constexpr uint64_t FNV_BASIS = 1469598103934665603ull;
 constexpr uint64_t FNV_PRIME = 1099511628211ull;
 constexpr int kMaxWaves = 16;
+constexpr int kFrontCap = 128;   // frontier records kept in LDS
+constexpr int kWinBits = 8;
+constexpr int kWinCap = 1 << kWinBits;   // LDS winner table (variables implied in a round)
+constexpr int kWinProbe = 32;
+constexpr int kImplCap = 128;    // LDS implication slots (Deps candidate and record)
+constexpr uint32_t SLOT_TAG = 0x80000000u;
 
 // Uniform search state: identical in every lane.
 struct Ctl {
     int32_t inst, A, Rh, V, nS, u0, u1, has_empty;
     int32_t cdl, qh, qt, n_learned, pend_kind, pending, status, init_done, last_step, pool_top;
     int32_t use_score, consec, dec_open;   // score-driven Decision and its fallback
+    int32_t fr_ok;    // the LDS records describe the frontier trail[qh..qt)
     int64_t learned_lits, rounds, props, decisions, conflicts, learned, learned_len, gate_fail,
             completes, steps, visits, checks;
     uint64_t hash;
@@ -65,7 +72,7 @@ struct Ctl {
 // LDS words through which lanes exchange per-phase results.
 struct Scr {
     unsigned long long conf_key;
-    int32_t tail, clash, changed, pool_top, cap_err;
+    int32_t tail, clash, changed, pool_top, cap_err, nimpl;
     int32_t flag[kMaxWaves];
     int32_t wsum[kMaxWaves + 1];
     unsigned long long red[kMaxWaves];
@@ -85,6 +92,17 @@ struct Ctx {
     // LDS
     uint32_t *valb, *pendb;
     int32_t *sOff, *sS0, *sCs, *sL0;
+    // frontier records: map segment (start, size) and learned occurrence
+    // list (start, size) of each frontier variable's true literal, and the
+    // variables the current round implies (in trail order)
+    int32_t *fS0, *fCs, *fL0, *fCl, *fNew, *fSlot;
+    // the round's winner table (variable -> lowest implier key) and the
+    // implication slots (W = 1): the Deps of an implier's other variables
+    // and the record of the literal it makes true, computed at visit time so
+    // that applying the winner reads LDS only
+    int32_t* tKey;
+    unsigned long long *tWin, *iDeps;
+    int32_t *iS0, *iCs, *iL0, *iCl;
     unsigned long long* sB;
     Scr* scr;
     int32_t W, T, tid, lane, wid, nw;
@@ -243,6 +261,39 @@ DEV unsigned long long alldec_word(int w, int cdl, int W) {
     return m << (a - b0);
 }
 
+DEV int tab_hash(int x) { return (int)(((uint32_t)x * 0x9E3779B1u) >> (32 - kWinBits)); }
+
+// Slot of variable x in the round's winner table (inserted if absent);
+// -1 when the probe window is full (the global table is used instead).
+DEV int tab_insert(Ctx& c, int x) {
+    const int h = tab_hash(x);
+    for (int p = 0; p < kWinProbe; ++p) {
+        const int sl = (h + p) & (kWinCap - 1);
+        const int old = atomicCAS(&c.tKey[sl], -1, x);
+        if (old == -1 || old == x) return sl;
+    }
+    return -1;
+}
+
+// Slot of x once every insertion of the round is done; -1 if absent.
+DEV int tab_find(const Ctx& c, int x) {
+    const int h = tab_hash(x);
+    for (int p = 0; p < kWinProbe; ++p) {
+        const int sl = (h + p) & (kWinCap - 1);
+        const int key = c.tKey[sl];
+        if (key == x) return sl;
+        if (key == -1) return -1;
+    }
+    return -1;
+}
+
+DEV void tab_clear_all(Ctx& c) {
+    for (int i = c.tid; i < kWinCap; i += c.T) {
+        c.tKey[i] = -1;
+        c.tWin[i] = WIN_NONE;
+    }
+}
+
 // --------------------------------------------------------- state moves
 DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     const InstDesc& d = a.inst[inst];
@@ -322,6 +373,8 @@ DEV void reset_search(Ctx& c, Ctl& k) {
     k.consec = 0;
     k.dec_open = 0;
     k.t_round = k.t_learn = k.t_decide = k.t_gate = 0;
+    k.fr_ok = 0;
+    tab_clear_all(c);
     bar();
 }
 
@@ -369,6 +422,8 @@ DEV void load_ctrl(Ctx& c, Ctl& k) {
     k.dec_open = uni(g.dec_open);
     k.steps = 0;
     k.t_round = k.t_learn = k.t_decide = k.t_gate = 0;
+    k.fr_ok = 0;
+    tab_clear_all(c);
     bar();
 }
 
@@ -464,6 +519,18 @@ DEV void step_init(Ctx& c, Ctl& k) {
         k.qh = q0;
         k.qt = q1;
     }
+    k.fr_ok = 0;
+}
+
+// Frontier record i for variable x taking value `code`: where the visits of
+// its now-true literal are (static map segment, learned occurrence list).
+DEV void put_record(Ctx& c, int i, int x, uint32_t code) {
+    const int li = 2 * x + (code == VF ? 1 : 0);
+    const int s0 = c.MO[li];
+    c.fS0[i] = s0;
+    c.fCs[i] = c.MO[li + 1] - s0;
+    c.fL0[i] = c.lptr[li];
+    c.fCl[i] = c.ln[li];
 }
 
 // Classification of one visited nogood against the round's snapshot.  A
@@ -476,7 +543,9 @@ DEV void step_init(Ctx& c, Ctl& k) {
 // of the other value.
 DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eidx, int pass) {
     int len, open = 0, u = 0;
-    if (e.o1 != kLongNogood) {
+    const bool inl = e.o1 != kLongNogood;
+    const int32_t* lits = nullptr;
+    if (inl) {
         const int o1 = e.o1, o2 = e.o2;
         len = 1 + (o1 != 0 ? 1 : 0) + (o2 != 0 ? 1 : 0);
         if (pass == 0) {
@@ -495,7 +564,6 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
         }
     } else {
         eidx = NO_ENTRY;
-        const int32_t* lits;
         ng_span(c, k, id, lits, len);
         if (pass == 0) {
             c.my_visits += 1ull;
@@ -521,18 +589,51 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
     const uint32_t code = u > 0 ? VF : VT;   // implied value of x
     if (pass == 0) {
         const uint32_t hi = (uint32_t)(id * 2 + (code == VF ? 1 : 0));
-        min_wg(&c.win[x], ((unsigned long long)hi << 32) | eidx);
+        uint32_t lo = eidx;
+        if (c.W == 1) {
+            // the Deps this implication would give x (the snapshot's Deps of
+            // the nogood's other variables) and the record of the literal it
+            // makes true, kept in a slot in case this implier wins
+            unsigned long long d = 0ull;
+            if (inl) {
+                d = c.deps[lvar(e.self)];
+                if (e.o1 != 0 && lvar(e.o1) != x) d |= c.deps[lvar(e.o1)];
+                if (e.o2 != 0 && lvar(e.o2) != x) d |= c.deps[lvar(e.o2)];
+            } else {
+                for (int q = 0; q < len; ++q) {
+                    const int y = lvar(lits[q]);
+                    if (y != x) d |= c.deps[y];
+                }
+            }
+            const int li = 2 * x + (code == VF ? 1 : 0);
+            const int s0 = c.MO[li], s1 = c.MO[li + 1], l0 = c.lptr[li], cl = c.ln[li];
+            const int sl = atomicAdd(&c.scr->nimpl, 1);
+            if (sl < kImplCap) {
+                c.iDeps[sl] = d;
+                c.iS0[sl] = s0;
+                c.iCs[sl] = s1 - s0;
+                c.iL0[sl] = l0;
+                c.iCl[sl] = cl;
+                lo = SLOT_TAG | (uint32_t)sl;
+            }
+        }
+        const unsigned long long key = ((unsigned long long)hi << 32) | lo;
+        const int t = tab_insert(c, x);
+        if (t >= 0) atomicMin(&c.tWin[t], key);
+        else min_wg(&c.win[x], key);
         uint32_t sh = (uint32_t)(x & 15) << 1;
         uint32_t old = atomicOr(&c.pendb[x >> 4], code << sh);
         uint32_t ob = (old >> sh) & 3u;
         if (ob == 0u) {
-            int pos = atomicAdd(&c.scr->tail, 1);
+            const int pos = atomicAdd(&c.scr->tail, 1);
             c.trail[pos] = x;
+            if (pos - k.qt < kFrontCap) c.fNew[pos - k.qt] = x;
         } else if ((ob | code) == 3u) {
             c.scr->clash = 1;
         }
     } else {
-        const unsigned long long key = ld_wg(&c.win[x]);
+        const int t = tab_find(c, x);
+        const unsigned long long key = t >= 0 ? c.tWin[t] : ld_wg(&c.win[x]);
         const uint32_t wcode = ((key >> 32) & 1ull) ? VF : VT;
         if (wcode != code)
             atomicMin(&c.scr->conf_key, ((unsigned long long)(uint32_t)len << 32) | (uint32_t)id);
@@ -548,13 +649,20 @@ DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
         const int f = base + tid;
         int s0 = 0, cs = 0, l0 = 0, cl = 0;
         if (f < qt) {
-            int v = c.trail[f];
-            int L = vget(c.valb, v) == VT ? v : -v;
-            int li = lidx(L);
-            s0 = c.MO[li];
-            cs = c.MO[li + 1] - s0;
-            l0 = c.lptr[li];
-            cl = c.ln[li];
+            if (k.fr_ok) {
+                s0 = c.fS0[f - qh];
+                cs = c.fCs[f - qh];
+                l0 = c.fL0[f - qh];
+                cl = c.fCl[f - qh];
+            } else {
+                int v = c.trail[f];
+                int L = vget(c.valb, v) == VT ? v : -v;
+                int li = lidx(L);
+                s0 = c.MO[li];
+                cs = c.MO[li + 1] - s0;
+                l0 = c.lptr[li];
+                cl = c.ln[li];
+            }
         }
         int total;
         int off = block_excl_scan(c, cs + cl, &total);
@@ -592,63 +700,100 @@ DEV void step_round(Ctx& c, Ctl& k) {
     c.scr->conf_key = ~0ull;
     c.scr->clash = 0;
     c.scr->tail = qt;
+    c.scr->nimpl = 0;
     bar();
     visit_pass(c, k, qh, qt, 0);
     bar();
     if (uni(c.scr->clash)) {
         visit_pass(c, k, qh, qt, 1);
-            bar();
+        bar();
     }
     const int nt = uni(c.scr->tail);
     // apply every implication, its Deps being the OR of the Deps of the
-    // other variables of the winning nogood (mk_dl_bitmap)
+    // other variables of the winning nogood (mk_dl_bitmap).  The implied
+    // variables come from LDS when they fit, and so does the winner: its
+    // key from the LDS table, its Deps and frontier record from its slot;
+    // the apply also writes the next round's frontier records
+    const bool rec = nt - qt <= kFrontCap;
     for (int i = qt + tid; i < nt; i += T) {
-        const int x = c.trail[i];
-        const unsigned long long key = ld_wg(&c.win[x]);
+        const int x = rec ? c.fNew[i - qt] : c.trail[i];
+        const int t = tab_find(c, x);
+        unsigned long long key;
+        if (t >= 0) {
+            key = c.tWin[t];
+        } else {
+            key = ld_wg(&c.win[x]);
+            st_wg(&c.win[x], WIN_NONE);
+        }
+        if (rec) c.fSlot[i - qt] = t;
         const int id = (int)(key >> 33);
         const uint32_t code = ((key >> 32) & 1ull) ? VF : VT;
-        const uint32_t eidx = (uint32_t)key;
-        const int32_t* lits;
-        int len;
-        int32_t inl[3];
-        if (eidx != NO_ENTRY) {
-            // the winner is a short static nogood: its literals are in the entry
-            const MapEntry e = c.ME[eidx];
-            inl[0] = e.self;
-            inl[1] = e.o1;
-            inl[2] = e.o2;
-            lits = inl;
-            len = 1 + (e.o1 != 0 ? 1 : 0) + (e.o2 != 0 ? 1 : 0);
-        } else {
-            ng_span(c, k, id, lits, len);
-        }
+        const uint32_t lo = (uint32_t)key;
         uint64_t* dx = c.deps + (size_t)x * W;
-        if (W == 1) {
-            unsigned long long acc = 0ull;
-            for (int q = 0; q < len; ++q) {
-                int y = lvar(lits[q]);
-                if (y != x) acc |= c.deps[y];
+        if (lo != NO_ENTRY && (lo & SLOT_TAG)) {
+            const int sl = (int)(lo & ~SLOT_TAG);
+            dx[0] = c.iDeps[sl];
+            if (rec) {
+                c.fS0[i - qt] = c.iS0[sl];
+                c.fCs[i - qt] = c.iCs[sl];
+                c.fL0[i - qt] = c.iL0[sl];
+                c.fCl[i - qt] = c.iCl[sl];
             }
-            dx[0] = acc;
         } else {
-            for (int w = 0; w < W; ++w) dx[w] = 0ull;
-            for (int q = 0; q < len; ++q) {
-                int y = lvar(lits[q]);
-                if (y == x) continue;
-                const uint64_t* dy = c.deps + (size_t)y * W;
-                for (int w = 0; w < W; ++w) dx[w] |= dy[w];
+            const int32_t* lits;
+            int len;
+            int32_t inl[3];
+            if (lo != NO_ENTRY) {
+                // the winner is a short static nogood: its literals are in the entry
+                const MapEntry e = c.ME[lo];
+                inl[0] = e.self;
+                inl[1] = e.o1;
+                inl[2] = e.o2;
+                lits = inl;
+                len = 1 + (e.o1 != 0 ? 1 : 0) + (e.o2 != 0 ? 1 : 0);
+            } else {
+                ng_span(c, k, id, lits, len);
             }
+            if (W == 1) {
+                unsigned long long acc = 0ull;
+                for (int q = 0; q < len; ++q) {
+                    int y = lvar(lits[q]);
+                    if (y != x) acc |= c.deps[y];
+                }
+                dx[0] = acc;
+            } else {
+                for (int w = 0; w < W; ++w) dx[w] = 0ull;
+                for (int q = 0; q < len; ++q) {
+                    int y = lvar(lits[q]);
+                    if (y == x) continue;
+                    const uint64_t* dy = c.deps + (size_t)y * W;
+                    for (int w = 0; w < W; ++w) dx[w] |= dy[w];
+                }
+            }
+            if (rec) put_record(c, i - qt, x, code);
         }
         c.lvl[x] = cdl;
         vset(c.valb, x, code);
         vclr(c.pendb, x);
-        st_wg(&c.win[x], WIN_NONE);
     }
     bar();
     const unsigned long long ck = (unsigned long long)uni64((int64_t)c.scr->conf_key);
+    // the winner table is empty again for the next round
+    if (rec) {
+        for (int i = tid; i < nt - qt; i += T) {
+            const int t = c.fSlot[i];
+            if (t >= 0) {
+                c.tKey[t] = -1;
+                c.tWin[t] = WIN_NONE;
+            }
+        }
+    } else {
+        tab_clear_all(c);
+    }
     bar();
     k.qh = qt;
     k.qt = nt;
+    k.fr_ok = rec ? 1 : 0;
     k.rounds += 1;
     k.props += nt - qt;
     if (ck != ~0ull) {
@@ -830,10 +975,12 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     c.trail[start] = x;
     bar();
     for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
+    put_record(c, 0, x, top > 0 ? VF : VT);   // identical from every lane
     bar();
     k.cdl = bj;
     k.qh = start;
     k.qt = start + 1;
+    k.fr_ok = 1;
     k.pending = -1;
     k.pend_kind = 0;
     k.n_learned += 1;
@@ -858,14 +1005,27 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
     // key: head score (signed, biased to keep its order) then lowest rule
     const int32_t* score = k.use_score ? c.RS : c.RO;
     unsigned long long best = 0ull;
-    for (int j = tid; j < Rh; j += T) {
-        int p = c.RH[j];
-        if (vget(c.valb, p) != 0u) continue;
-        int t = A + 3 * j + 2;
-        if (vget(c.valb, t) != VT || vget(c.valb, t + 1) == VF) continue;
-        unsigned long long key = ((unsigned long long)((uint32_t)score[j] ^ 0x80000000u) << 32) |
-                                 (unsigned long long)(0xffffffffu - (uint32_t)j);
-        best = key > best ? key : best;
+    // four rules per lane at a time: their loads are issued together
+    constexpr int U = 4;
+    for (int j0 = tid; j0 < Rh; j0 += U * T) {
+        int hp[U], sc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * T;
+            hp[u] = j < Rh ? c.RH[j] : 0;
+            sc[u] = j < Rh ? score[j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * T;
+            if (j >= Rh || vget(c.valb, hp[u]) != 0u) continue;
+            const int t = A + 3 * j + 2;
+            if (vget(c.valb, t) != VT || vget(c.valb, t + 1) == VF) continue;
+            const unsigned long long key =
+                ((unsigned long long)((uint32_t)sc[u] ^ 0x80000000u) << 32) |
+                (unsigned long long)(0xffffffffu - (uint32_t)j);
+            best = key > best ? key : best;
+        }
     }
     best = block_max_u64(c, best);
     bar();
@@ -881,10 +1041,12 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         c.lvl[b] = ncdl;
         c.trail[k.qt] = b;
         vset(c.valb, b, VT);
-            bar();
+        put_record(c, 0, b, VT);             // identical from every lane
+        bar();
         k.cdl = ncdl;
         k.qh = k.qt;
         k.qt = k.qt + 1;
+        k.fr_ok = 1;
         k.decisions += 1;
         k.dec_open = 1;
         k.hash = fnv(k.hash, 1);
@@ -912,6 +1074,7 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
     k.hash = fnv(k.hash, n);
     k.qh = k.qt;
     k.qt = nt;
+    k.fr_ok = 0;
     if (n == 0) k.status = ST_E_INTERNAL;
     return STEP_COMPLETE;
 }
@@ -1073,8 +1236,10 @@ DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a, uint64_t t0) {
     bar();
 }
 
+// Three waves per SIMD: the register budget (168 VGPRs) at which the
+// search keeps six 128-thread workgroups resident per CU.
 template <int MAXT>
-__global__ __launch_bounds__(MAXT) void k_search(KArgs a) {
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void k_search(KArgs a) {
     HIP_DYNAMIC_SHARED(unsigned long long, smem64);  // 8-byte aligned base
     __shared__ Scr scr;
     Ctx c;
@@ -1094,10 +1259,23 @@ __global__ __launch_bounds__(MAXT) void k_search(KArgs a) {
         c.valb = (uint32_t*)p; p += sizeof(uint32_t) * a.words;
         c.pendb = (uint32_t*)p; p += sizeof(uint32_t) * a.words;
         c.sB = (unsigned long long*)p; p += sizeof(unsigned long long) * kMaxW;
+        c.tWin = (unsigned long long*)p; p += sizeof(unsigned long long) * kWinCap;
+        c.iDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * kImplCap;
+        c.tKey = (int32_t*)p; p += sizeof(int32_t) * kWinCap;
+        c.iS0 = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
+        c.iCs = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
+        c.iL0 = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
+        c.iCl = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
         c.sOff = (int32_t*)p; p += sizeof(int32_t) * MAXT;
         c.sS0 = (int32_t*)p; p += sizeof(int32_t) * MAXT;
         c.sCs = (int32_t*)p; p += sizeof(int32_t) * MAXT;
         c.sL0 = (int32_t*)p; p += sizeof(int32_t) * MAXT;
+        c.fS0 = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
+        c.fCs = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
+        c.fL0 = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
+        c.fCl = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
+        c.fNew = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
+        c.fSlot = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
     }
     const uint64_t t0 = wall_clock64();
     if (a.mode == MODE_SOLVE) {
@@ -1127,7 +1305,9 @@ __global__ __launch_bounds__(MAXT) void k_search(KArgs a) {
 // ------------------------------------------------------------ launchers
 size_t lds_bytes(int threads, int words) {
     return sizeof(uint32_t) * 2 * (size_t)words + sizeof(unsigned long long) * kMaxW +
-           sizeof(int32_t) * 4 * (size_t)threads;
+           sizeof(int32_t) * 4 * (size_t)threads + sizeof(int32_t) * 6 * (size_t)kFrontCap +
+           (sizeof(unsigned long long) + sizeof(int32_t)) * (size_t)kWinCap +
+           (sizeof(unsigned long long) + 4 * sizeof(int32_t)) * (size_t)kImplCap;
 }
 
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {

@@ -953,7 +953,9 @@ int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
     if (loff[0] != 0 || loff[nL] != st->learned_lits) return fail(ASP_E_INVALID, "learned offsets");
     for (int64_t q = 0; q < st->learned_lits; ++q) {
         int32_t l = st->learned[q];
-        if (l == 0 || l > V || l < -V) return fail(ASP_E_INVALID, "learned literal out of range");
+        // learned nogoods hold decision literals T b_r only
+        if (l <= A || l > V || (l - A - 1) % 3 != 0)
+            return fail(ASP_E_INVALID, "learned literal is not a decision literal T b_r");
         llits[q] = l;
     }
     const size_t NL = 2 * ((size_t)V + 1);

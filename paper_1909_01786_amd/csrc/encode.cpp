@@ -173,13 +173,21 @@ int encode_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
         for (int64_t id = 0; id < G; ++id) {
             const int32_t b = P->ng_off[id], e = P->ng_off[id + 1];
             for (int32_t k = b; k < e; ++k) {
-                MapEntry m{(int32_t)id, P->ng_lits[k], 0, 0};
+                MapEntry m{(int32_t)id, P->ng_lits[k], 0, 0, 0, 0, 0, 0};
                 if (e - b > 3) {
                     m.o1 = kLongNogood;
                 } else {
                     int32_t* o = &m.o1;
-                    for (int32_t q = b; q < e; ++q)
-                        if (q != k) *o++ = P->ng_lits[q];
+                    int32_t* seg = &m.a1;
+                    for (int32_t q = b; q < e; ++q) {
+                        if (q == k) continue;
+                        const int32_t l = P->ng_lits[q];
+                        const int64_t ci = lit_index(-l);   // the complement's segment
+                        *o++ = l;
+                        seg[0] = P->map_off[ci];
+                        seg[1] = P->map_off[ci + 1] - P->map_off[ci];
+                        seg += 2;
+                    }
                 }
                 P->map_ent[fill[lit_index(P->ng_lits[k])]++] = m;
             }

@@ -20,10 +20,13 @@ constexpr int kAlign = 256;
 
 // One entry of the literal -> nogood map: the nogood's id, the map's own
 // literal, and the nogood's other literals when it has at most three (0
-// pads the unused ones).  A longer nogood has o1 = kLongNogood and is read
-// from the nogood CSR.  A visit of a short nogood is one 16-byte load.
-struct alignas(16) MapEntry {
+// pads the unused ones), each with the map segment (start, size) of its
+// complement -- the literal a unit nogood makes true.  A longer nogood has
+// o1 = kLongNogood and is read from the nogood CSR.  A visit of a short
+// nogood is one 32-byte load.
+struct alignas(32) MapEntry {
     int32_t id, self, o1, o2;
+    int32_t a1, n1, a2, n2;
 };
 constexpr int32_t kLongNogood = (int32_t)0x80000000;
 

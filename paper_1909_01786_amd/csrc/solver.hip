@@ -102,6 +102,9 @@ struct Ctx {
     // that applying the winner reads LDS only
     int32_t* tKey;
     unsigned long long *tWin, *iDeps;
+    // Deps word of each frontier variable (W = 1), per record and per lane
+    // of the visit pass
+    unsigned long long *fDeps, *sDeps;
     int32_t *iS0, *iCs, *iL0, *iCl;
     unsigned long long* sB;
     Scr* scr;
@@ -158,22 +161,6 @@ DEV int wave_incl_scan(int x, int lane) {
 }
 
 // Exclusive scan over the block; every lane must call it.
-DEV int block_excl_scan(Ctx& c, int x, int* total) {
-    const int inc = wave_incl_scan(x, c.lane);
-    const int wtot = __shfl(inc, 63, 64);
-    bar();
-    c.scr->wsum[c.wid] = wtot;   // every lane of the wave stores the same value
-    bar();
-    int before = 0, all = 0;
-    for (int i = 0; i < c.nw; ++i) {
-        int s = c.scr->wsum[i];
-        before += i < c.wid ? s : 0;
-        all += s;
-    }
-    *total = uni(all);
-    return inc - x + before;
-}
-
 DEV unsigned long long block_max_u64(Ctx& c, unsigned long long x) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
@@ -522,15 +509,17 @@ DEV void step_init(Ctx& c, Ctl& k) {
     k.fr_ok = 0;
 }
 
-// Frontier record i for variable x taking value `code`: where the visits of
-// its now-true literal are (static map segment, learned occurrence list).
-DEV void put_record(Ctx& c, int i, int x, uint32_t code) {
+// Frontier record i for variable x taking value `code` with Deps word d0:
+// where the visits of its now-true literal are (static map segment,
+// learned occurrence list).
+DEV void put_record(Ctx& c, int i, int x, uint32_t code, unsigned long long d0) {
     const int li = 2 * x + (code == VF ? 1 : 0);
     const int s0 = c.MO[li];
     c.fS0[i] = s0;
     c.fCs[i] = c.MO[li + 1] - s0;
     c.fL0[i] = c.lptr[li];
     c.fCl[i] = c.ln[li];
+    c.fDeps[i] = d0;
 }
 
 // Classification of one visited nogood against the round's snapshot.  A
@@ -541,7 +530,8 @@ DEV void put_record(Ctx& c, int i, int x, uint32_t code) {
 // implied value, then the map entry the Deps will be read from); pass 1:
 // conflicts of unit nogoods that lost their variable to a lower-id implier
 // of the other value.
-DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eidx, int pass) {
+DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eidx,
+                   unsigned long long selfd, int pass) {
     int len, open = 0, u = 0;
     const bool inl = e.o1 != kLongNogood;
     const int32_t* lits = nullptr;
@@ -594,24 +584,36 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
             // the Deps this implication would give x (the snapshot's Deps of
             // the nogood's other variables) and the record of the literal it
             // makes true, kept in a slot in case this implier wins
-            unsigned long long d = 0ull;
+            // (the map literal's variable is the frontier variable: its Deps
+            // come with the frontier; a short nogood's entry holds the map
+            // segment of each literal it can make true; learned occurrence
+            // lists exist only for decision literals T b_r)
+            unsigned long long d;
+            int s0, cs;
             if (inl) {
-                d = c.deps[lvar(e.self)];
+                d = selfd;
                 if (e.o1 != 0 && lvar(e.o1) != x) d |= c.deps[lvar(e.o1)];
                 if (e.o2 != 0 && lvar(e.o2) != x) d |= c.deps[lvar(e.o2)];
+                s0 = u == e.o1 ? e.a1 : e.a2;
+                cs = u == e.o1 ? e.n1 : e.n2;
             } else {
+                d = 0ull;
                 for (int q = 0; q < len; ++q) {
                     const int y = lvar(lits[q]);
                     if (y != x) d |= c.deps[y];
                 }
+                const int li = 2 * x + (code == VF ? 1 : 0);
+                s0 = c.MO[li];
+                cs = c.MO[li + 1] - s0;
             }
-            const int li = 2 * x + (code == VF ? 1 : 0);
-            const int s0 = c.MO[li], s1 = c.MO[li + 1], l0 = c.lptr[li], cl = c.ln[li];
+            const bool dec_lit = code == VT && x > k.A && (x - k.A - 1) % 3 == 0;
+            const int l0 = dec_lit ? c.lptr[2 * x] : 0;
+            const int cl = dec_lit ? c.ln[2 * x] : 0;
             const int sl = atomicAdd(&c.scr->nimpl, 1);
             if (sl < kImplCap) {
                 c.iDeps[sl] = d;
                 c.iS0[sl] = s0;
-                c.iCs[sl] = s1 - s0;
+                c.iCs[sl] = cs;
                 c.iL0[sl] = l0;
                 c.iCl[sl] = cl;
                 lo = SLOT_TAG | (uint32_t)sl;
@@ -642,18 +644,20 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
 
 // Spread the visits of frontier trail[qh..qt) over the block: each frontier
 // variable contributes its static map segment and its learned occurrence
-// list; an exclusive scan of the segment sizes gives each lane its visits.
+// list; a scan of the segment sizes gives each lane its visits.
 DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
     const int T = c.T, tid = c.tid;
     for (int base = qh; base < qt; base += T) {
         const int f = base + tid;
         int s0 = 0, cs = 0, l0 = 0, cl = 0;
+        unsigned long long sd = 0ull;
         if (f < qt) {
             if (k.fr_ok) {
                 s0 = c.fS0[f - qh];
                 cs = c.fCs[f - qh];
                 l0 = c.fL0[f - qh];
                 cl = c.fCl[f - qh];
+                sd = c.fDeps[f - qh];
             } else {
                 int v = c.trail[f];
                 int L = vget(c.valb, v) == VT ? v : -v;
@@ -662,31 +666,47 @@ DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
                 cs = c.MO[li + 1] - s0;
                 l0 = c.lptr[li];
                 cl = c.ln[li];
+                sd = c.deps[(size_t)v * c.W];
             }
         }
-        int total;
-        int off = block_excl_scan(c, cs + cl, &total);
-        c.sOff[tid] = off;
+        // wave-local exclusive offsets of the visit counts, and the wave
+        // totals: one barrier makes every visit's position known
+        const int cnt_all = cs + cl;
+        const int inc = wave_incl_scan(cnt_all, c.lane);
+        c.sOff[tid] = inc - cnt_all;
         c.sS0[tid] = s0;
         c.sCs[tid] = cs;
         c.sL0[tid] = l0;
+        c.sDeps[tid] = sd;
+        c.scr->wsum[c.wid] = __shfl(inc, 63, 64);   // identical from the wave's lanes
         bar();
         const int nf = (qt - base) < T ? (qt - base) : T;
+        const int nwv = (nf + 63) >> 6;
+        int total = 0;
+        for (int w = 0; w < nwv; ++w) total += c.scr->wsum[w];
+        total = uni(total);
         for (int q = tid; q < total; q += T) {
-            int lo = 0, hi = nf - 1;
+            // the wave whose lanes hold visit q, then the lane within it
+            int w = 0, wb = 0;
+            while (w + 1 < nwv && wb + c.scr->wsum[w] <= q) {
+                wb += c.scr->wsum[w];
+                ++w;
+            }
+            const int qq = q - wb;
+            int lo = w * 64, hi = min(nf, w * 64 + 64) - 1;
             while (lo < hi) {
                 int mid = (lo + hi + 1) >> 1;
-                if (c.sOff[mid] <= q) lo = mid; else hi = mid - 1;
+                if (c.sOff[mid] <= qq) lo = mid; else hi = mid - 1;
             }
-            const int j = q - c.sOff[lo];
+            const int j = qq - c.sOff[lo];
             const int cnt = c.sCs[lo];
             if (j < cnt) {
                 const uint32_t eidx = (uint32_t)(c.sS0[lo] + j);
                 const MapEntry e = c.ME[eidx];
-                visit_one(c, k, e.id, e, eidx, pass);
+                visit_one(c, k, e.id, e, eidx, c.sDeps[lo], pass);
             } else {
-                const MapEntry none{0, 0, kLongNogood, 0};
-                visit_one(c, k, c.pool[c.sL0[lo] + (j - cnt)], none, NO_ENTRY, pass);
+                const MapEntry none{0, 0, kLongNogood, 0, 0, 0, 0, 0};
+                visit_one(c, k, c.pool[c.sL0[lo] + (j - cnt)], none, NO_ENTRY, c.sDeps[lo], pass);
             }
         }
         bar();
@@ -732,12 +752,14 @@ DEV void step_round(Ctx& c, Ctl& k) {
         uint64_t* dx = c.deps + (size_t)x * W;
         if (lo != NO_ENTRY && (lo & SLOT_TAG)) {
             const int sl = (int)(lo & ~SLOT_TAG);
-            dx[0] = c.iDeps[sl];
+            const unsigned long long d0 = c.iDeps[sl];
+            dx[0] = d0;
             if (rec) {
                 c.fS0[i - qt] = c.iS0[sl];
                 c.fCs[i - qt] = c.iCs[sl];
                 c.fL0[i - qt] = c.iL0[sl];
                 c.fCl[i - qt] = c.iCl[sl];
+                c.fDeps[i - qt] = d0;
             }
         } else {
             const int32_t* lits;
@@ -770,7 +792,7 @@ DEV void step_round(Ctx& c, Ctl& k) {
                     for (int w = 0; w < W; ++w) dx[w] |= dy[w];
                 }
             }
-            if (rec) put_record(c, i - qt, x, code);
+            if (rec) put_record(c, i - qt, x, code, dx[0]);
         }
         c.lvl[x] = cdl;
         vset(c.valb, x, code);
@@ -790,7 +812,7 @@ DEV void step_round(Ctx& c, Ctl& k) {
     } else {
         tab_clear_all(c);
     }
-    bar();
+    // (the step loop's barrier orders the table clearing before the next use)
     k.qh = qt;
     k.qt = nt;
     k.fr_ok = rec ? 1 : 0;
@@ -975,7 +997,7 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     c.trail[start] = x;
     bar();
     for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
-    put_record(c, 0, x, top > 0 ? VF : VT);   // identical from every lane
+    put_record(c, 0, x, top > 0 ? VF : VT, c.deps[(size_t)x * W]);   // identical from every lane
     bar();
     k.cdl = bj;
     k.qh = start;
@@ -1041,7 +1063,7 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         c.lvl[b] = ncdl;
         c.trail[k.qt] = b;
         vset(c.valb, b, VT);
-        put_record(c, 0, b, VT);             // identical from every lane
+        put_record(c, 0, b, VT, bit < 64 ? (1ull << bit) : 0ull);   // identical from every lane
         bar();
         k.cdl = ncdl;
         k.qh = k.qt;
@@ -1169,9 +1191,12 @@ DEV void run_search(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model, uint64_t t0)
             } else if (a.max_steps >= 0 && k.steps >= a.max_steps) {
                 k.status = ST_E_INTERNAL;
             }
-            // the clock is read per wave; the workgroup acts on the OR
-            int late = (a.max_ticks && (uint64_t)(wall_clock64() - t0) > a.max_ticks) ? 1 : 0;
-            if (block_any(c, late)) k.status = ST_E_TIMEOUT;
+            // the clock is read per wave, every 64 steps; the workgroup
+            // acts on the OR
+            if ((k.steps & 63) == 0) {
+                int late = (a.max_ticks && (uint64_t)(wall_clock64() - t0) > a.max_ticks) ? 1 : 0;
+                if (block_any(c, late)) k.status = ST_E_TIMEOUT;
+            }
         }
         int kind = STEP_DONE;
         if (!halt && k.status == ST_RUNNING) {
@@ -1261,6 +1286,8 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void 
         c.sB = (unsigned long long*)p; p += sizeof(unsigned long long) * kMaxW;
         c.tWin = (unsigned long long*)p; p += sizeof(unsigned long long) * kWinCap;
         c.iDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * kImplCap;
+        c.fDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * kFrontCap;
+        c.sDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * MAXT;
         c.tKey = (int32_t*)p; p += sizeof(int32_t) * kWinCap;
         c.iS0 = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
         c.iCs = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
@@ -1307,7 +1334,8 @@ size_t lds_bytes(int threads, int words) {
     return sizeof(uint32_t) * 2 * (size_t)words + sizeof(unsigned long long) * kMaxW +
            sizeof(int32_t) * 4 * (size_t)threads + sizeof(int32_t) * 6 * (size_t)kFrontCap +
            (sizeof(unsigned long long) + sizeof(int32_t)) * (size_t)kWinCap +
-           (sizeof(unsigned long long) + 4 * sizeof(int32_t)) * (size_t)kImplCap;
+           (sizeof(unsigned long long) + 4 * sizeof(int32_t)) * (size_t)kImplCap +
+           sizeof(unsigned long long) * ((size_t)kFrontCap + (size_t)threads);
 }
 
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {

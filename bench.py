@@ -386,6 +386,14 @@ def learned_leg(args, P, progs, plain_verd, stream, dev, lim, plain_ms_step, cth
     torch.cuda.synchronize()
     packed = P.scorer_weights(w)
     ms, walls = timed_steps(batch, lim, args.learned_steps, 1, before=lambda: batch.score(packed, ws))
+    # the scorer alone (all instances), between device synchronisations
+    sc_ms = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.score(packed, ws)
+        torch.cuda.synchronize()
+        sc_ms.append((time.perf_counter() - t0) * 1e3)
     verd, models, stats = batch.results()
     n_sat = int((verd == 1).sum())
     n_unsat = int((verd == 2).sum())
@@ -395,7 +403,8 @@ def learned_leg(args, P, progs, plain_verd, stream, dev, lim, plain_ms_step, cth
     ips = (n_sat + n_unsat) / (ms_step / 1000.0)
     plain_ips = int(((plain_verd == 1) | (plain_verd == 2)).sum()) / (plain_ms_step / 1000.0)
     return {
-        "weights": src, "ms_per_step": ms_step, "instances_per_s": ips,
+        "weights": src, "ms_per_step": ms_step, "scorer_ms": float(np.median(sc_ms)),
+        "instances_per_s": ips,
         "vs_plain_instances_per_s": ips / plain_ips if plain_ips > 0 else None,
         "verdicts": {"sat": n_sat, "unsat": n_unsat, "unknown": int((verd == 3).sum()),
                      "error": int((verd < 0).sum())},

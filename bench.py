@@ -243,6 +243,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-steps", type=int, default=2)
+    ap.add_argument("--graph-steps", type=int, default=2,
+                    help="replays of the batched solve as one HIP graph, timed after the eager steps")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the schedule (LDS classes, threads per class) by timing candidates first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--write-traffic", nargs=4, metavar="DIR",
@@ -287,6 +291,13 @@ def main():
     log(f"[bench] generated {args.n} programs in {t_gen:.1f}s, encoded in {t_enc:.1f}s, "
         f"{n_lits} nogood literals")
 
+    lim = P.limits(args.budget, args.max_ms)
+    tuned = None
+    if args.autotune:
+        from paper_1909_01786_amd.autotune import autotune
+        (args.classes, best), table = autotune(gp, lim, device=dev, log=log)
+        cth = list(best)
+        tuned = [{"classes": c, "class_threads": list(t), "ms": m} for c, t, m in table]
     stream = torch.cuda.Stream(device=dev)
     batch = P.Batch(gp, threads=args.threads, classes=args.classes, class_threads=cth)
     t0 = time.perf_counter()
@@ -295,7 +306,6 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] arena {batch.device_bytes / 2**30:.2f} GiB bound in {time.perf_counter() - t0:.1f}s")
 
-    lim = P.limits(args.budget, args.max_ms)
     ms, walls = timed_steps(batch, lim, args.steps, args.warmup)
     info, order = batch.launch_info()
     verd, models, stats = batch.results()
@@ -358,6 +368,19 @@ def main():
     }
     n_sat_checked, bad = verify_models(progs, verd, models)
     line["models_verified"] = {"sat": n_sat_checked, "not_stable": len(bad)}
+    if tuned:
+        line["autotune"] = tuned
+    if args.graph_steps > 0:
+        gms = []
+        for _ in range(args.graph_steps + 1):
+            batch.solve(lim, graph=True)
+            torch.cuda.synchronize()
+            gms.append(batch.last_ms())
+        gv, _, gst = batch.results()
+        same = np.array_equal(gv, verd) and all(
+            int(a[k]) == int(b[k]) for a, b in zip(gst, stats) for k in ("literal_checks", "trace_hash"))
+        line["graph"] = {"ms_per_step": float(np.mean(gms[1:])), "replays": args.graph_steps,
+                         "same_results_as_eager": bool(same)}
 
     if not args.no_learned:
         log("[bench] learned Decision leg")

@@ -280,10 +280,19 @@ int32_t asp_batch_bind(asp_batch *batch, void *dev_arena, uint64_t bytes,
                        void *stream);
 
 /* Enqueue the batched solve on stream (asynchronous): one launch per LDS
- * class, forked onto internal streams after the work already on `stream`
- * and joined back into it; each workgroup solves one instance to a verdict.
- * Results stay in the arena. */
+ * class -- the largest class on `stream` itself, the others forked onto
+ * internal streams after the work already on `stream` and joined back into
+ * it (at most four streams, so the classes run at once); each workgroup
+ * solves one instance to a verdict.  Results stay in the arena. */
 int32_t asp_solve_batch(asp_batch *batch, void *stream, const asp_limits *lim);
+
+/* The same batched solve as one HIP graph launch: the first call (and any
+ * call with other limits or another stream) captures the fork/join of the
+ * class launches into a graph; every call replays it with hipGraphLaunch on
+ * `stream` (a non-default stream).  Each launch resets the instances' search
+ * state itself, so replays need no clearing; asp_batch_last_ms times the
+ * replay, asp_batch_launch_info reports no per-class times for it. */
+int32_t asp_solve_batch_graph(asp_batch *batch, void *stream, const asp_limits *lim);
 
 /* Copy verdicts[n] (ASP_SAT/UNSAT/UNKNOWN or a negative error),
  * models[model_bytes] and stats[n] back (any may be NULL); synchronous. */
@@ -297,7 +306,8 @@ int32_t asp_batch_last_ms(asp_batch *batch, double *ms);
 /* The launches of the batch: *n_classes launches; launch c solves instances
  * order[first[c] .. first[c]+count[c]) with threads[c] threads per
  * workgroup, and took ms[c] milliseconds in the last asp_solve_batch (HIP
- * events on its stream; 0 before any solve).  Arrays of 4 entries (order:
+ * events on its stream; 0 before any solve and after a graph replay).
+ * Arrays of 4 entries (order:
  * n entries); any pointer may be NULL. */
 int32_t asp_batch_launch_info(asp_batch *batch, int32_t *n_classes, int32_t *first,
                               int32_t *count, int32_t *threads, double *ms, int32_t *order);

@@ -158,3 +158,43 @@ def scores(w: dict, prog) -> np.ndarray:
     g = graph_of(prog)
     s = forward(w, g)[: g.A + 1]
     return s.astype(np.int32)
+
+
+# ------------------------------------------------------------------ training
+def last_codes(w: dict, g: Graph) -> np.ndarray:
+    """Activation codes of every variable after the last layer ([V+1, 64])."""
+    trace: list = []
+    forward(w, g, trace)
+    return trace[-1][0]
+
+
+def readout_loss_grad(X: np.ndarray, y: np.ndarray, wb: np.ndarray):
+    """Mean binary cross-entropy of sigmoid(X w + b) against y, and its
+    gradient in (w, b).  X: [n, 64] float (codes / 256), y: 0/1."""
+    z = X @ wb[:64] + wb[64]
+    p = 1.0 / (1.0 + np.exp(-z))
+    loss = float(np.mean(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
+    r = (p - y) / len(y)
+    return loss, np.concatenate([X.T @ r, [r.sum()]])
+
+
+def train_readout(X: np.ndarray, y: np.ndarray, steps: int, lr: float, wb0=None,
+                  ridge: float = 0.0):
+    """Full-batch Adam (beta 0.9 / 0.999, eps 1e-8) on readout_loss_grad
+    (plus ridge/2 |w|^2 when ridge > 0; the device trains with none);
+    returns the weights after `steps` steps and the loss before each."""
+    wb = np.zeros(65) if wb0 is None else np.asarray(wb0, np.float64).copy()
+    m = np.zeros(65)
+    v = np.zeros(65)
+    losses = np.zeros(steps)
+    for t in range(steps):
+        losses[t], gr = readout_loss_grad(X, y, wb)
+        if ridge > 0:
+            losses[t] += 0.5 * ridge * float(wb[:64] @ wb[:64])
+            gr = gr + ridge * np.concatenate([wb[:64], [0.0]])
+        m = 0.9 * m + 0.1 * gr
+        v = 0.999 * v + 0.001 * gr * gr
+        mh = m / (1.0 - 0.9 ** (t + 1))
+        vh = v / (1.0 - 0.999 ** (t + 1))
+        wb = wb - lr * mh / (np.sqrt(vh) + 1e-8)
+    return wb, losses

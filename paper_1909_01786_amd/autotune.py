@@ -1,0 +1,59 @@
+"""Schedule autotuner for the batched solve.
+
+A schedule (number of LDS size classes, threads per workgroup of each class)
+changes how the batch is laid onto the GPU, never its results: each candidate
+is timed on the batch itself (one untimed launch, then `reps` timed ones with
+HIP events), its verdicts and search counters are checked equal to the first
+candidate's, and the fastest schedule is returned.
+
+    from paper_1909_01786_amd.autotune import autotune
+    best, table = autotune(programs, P.limits(2000, 150000))
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CANDIDATES = (
+    (4, (128, 128, 128, 128)),
+    (4, (256, 128, 128, 128)),
+    (4, (256, 256, 128, 128)),
+    (4, (512, 256, 128, 128)),
+    (3, (256, 128, 128)),
+    (2, (256, 128)),
+)
+
+_COUNTERS = ("rounds", "visits", "literal_checks", "propagations", "decisions", "conflicts",
+             "learned", "learned_len", "trace_hash")
+
+
+def autotune(programs, lim, candidates=CANDIDATES, device="cuda", reps: int = 1, log=None):
+    """programs: encoded Programs; returns ((classes, class_threads), table)
+    where table lists (classes, class_threads, ms) per candidate."""
+    import torch
+    from .binding import Batch
+    stream = torch.cuda.Stream(device=device)
+    table, ref = [], None
+    for classes, cth in candidates:
+        b = Batch(programs, threads=cth[-1], classes=classes, class_threads=list(cth))
+        with torch.cuda.stream(stream):
+            b.bind(device, stream=stream)
+        b.solve(lim)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            b.solve(lim)
+            torch.cuda.synchronize()
+            ms.append(b.last_ms())
+        verd, _, stats = b.results()
+        key = (verd.copy(), [tuple(int(s[k]) for k in _COUNTERS) for s in stats])
+        if ref is None:
+            ref = key
+        elif not (np.array_equal(ref[0], key[0]) and ref[1] == key[1]):
+            raise RuntimeError(f"schedule {classes}/{cth} changed the results")
+        table.append((classes, tuple(cth), float(np.median(ms))))
+        if log:
+            log(f"[autotune] classes {classes} threads {cth}: {table[-1][2]:.1f} ms")
+        del b
+        torch.cuda.empty_cache()
+    best = min(table, key=lambda t: t[2])
+    return (best[0], best[1]), table

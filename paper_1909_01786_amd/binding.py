@@ -130,7 +130,7 @@ EXPORTS = (
     "asp_status_str", "asp_last_error", "asp_set_scores", "asp_get_scores",
     "asp_batch_set_scores", "asp_batch_get_scores", "asp_scorer_workspace",
     "asp_batch_scorer_workspace", "asp_score_program", "asp_score_batch",
-    "asp_batch_train_readout", "asp_batch_launch_info",
+    "asp_batch_train_readout", "asp_batch_launch_info", "asp_solve_batch_graph",
 )
 
 _lib = None
@@ -161,6 +161,7 @@ def lib():
                                        C.POINTER(u64), C.POINTER(u64)]),
             "asp_batch_bind": (i32, [P, P, u64, P]),
             "asp_solve_batch": (i32, [P, P, C.POINTER(asp_limits)]),
+            "asp_solve_batch_graph": (i32, [P, P, C.POINTER(asp_limits)]),
             "asp_batch_results": (i32, [P, P, P, P, P]),
             "asp_batch_last_ms": (i32, [P, C.POINTER(C.c_double)]),
             "asp_batch_launch_info": (i32, [P, C.POINTER(i32), P, P, P, P, P]),
@@ -466,10 +467,12 @@ class Batch:
                                              _stream_ptr(self.stream)))
         return wb, loss
 
-    def solve(self, lim: asp_limits | None = None):
-        """Enqueue the batched solve on the stream (asynchronous)."""
-        _check(lib().asp_solve_batch(self._h, _stream_ptr(self.stream),
-                                     C.byref(lim) if lim else None))
+    def solve(self, lim: asp_limits | None = None, graph: bool = False):
+        """Enqueue the batched solve on the stream (asynchronous); with
+        graph=True as one replay of the captured HIP graph (the batch must be
+        bound on a non-default stream)."""
+        f = lib().asp_solve_batch_graph if graph else lib().asp_solve_batch
+        _check(f(self._h, _stream_ptr(self.stream), C.byref(lim) if lim else None))
 
     def launch_info(self):
         """[(first, count, threads, ms)] per launch class, and the instance order."""

@@ -142,6 +142,12 @@ struct asp_batch {
     std::vector<hipStream_t> streams;    // one per launch class (default priority)
     std::vector<hipEvent_t> ev_start, ev_join;  // per launch class (timed)
     bool timed = false;
+    bool class_timed = false;                    // ev_start/ev_join hold the last launches
+    // graph form of the batched solve (stream capture of the fork/join)
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t gstream = nullptr;
+    asp_limits glim{};
+    std::vector<hipEvent_t> ev_cjoin;           // capture-time joins (untimed)
 };
 
 namespace {
@@ -1187,7 +1193,10 @@ int32_t asp_solve_batch(asp_batch* b, void* stream, const asp_limits* lim) {
         b->ev_start.push_back(e0);
         b->ev_join.push_back(e1);
     }
-    while (nc > 1 && b->streams.size() < nc) {
+    // class 0 runs on the caller's stream, the others on internal streams:
+    // with the caller's stream that is at most four streams, one per
+    // hardware queue, so every class can run at once
+    while (nc > 1 && b->streams.size() < nc - 1) {
         hipStream_t t;
         HIPCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
         b->streams.push_back(t);
@@ -1208,15 +1217,80 @@ int32_t asp_solve_batch(asp_batch* b, void* stream, const asp_limits* lim) {
             const LaunchClass& lc = b->plan.classes[c];
             KArgs a = make_args(b->plan, b->arena, MODE_SOLVE, lc);
             apply_limits(a, b->plan, lim, di);
-            HIPCHK(hipStreamWaitEvent(b->streams[c], b->ev_fork, 0));
-            HIPCHK(hipEventRecord(b->ev_start[c], b->streams[c]));
-            HIPCHK(launch_search(a, lc.threads, lc.count, lc.lds, b->streams[c]));
-            HIPCHK(hipEventRecord(b->ev_join[c], b->streams[c]));
+            hipStream_t cs = c == 0 ? s : b->streams[c - 1];
+            if (c > 0) HIPCHK(hipStreamWaitEvent(cs, b->ev_fork, 0));
+            HIPCHK(hipEventRecord(b->ev_start[c], cs));
+            HIPCHK(launch_search(a, lc.threads, lc.count, lc.lds, cs));
+            HIPCHK(hipEventRecord(b->ev_join[c], cs));
         }
-        for (size_t c = 0; c < nc; ++c) HIPCHK(hipStreamWaitEvent(s, b->ev_join[c], 0));
+        for (size_t c = 1; c < nc; ++c) HIPCHK(hipStreamWaitEvent(s, b->ev_join[c], 0));
     }
     HIPCHK(hipEventRecord(b->ev1, s));
     b->timed = true;
+    b->class_timed = true;
+    return ASP_OK;
+}
+
+int32_t asp_solve_batch_graph(asp_batch* b, void* stream, const asp_limits* lim) {
+    if (!b || !b->bound) return fail(ASP_E_STATE, "batch not bound");
+    if (!stream) return fail(ASP_E_INVALID, "graph launches need a non-default stream");
+    if (b->opt.decision == ASP_DECISION_SCORE && b->n_ready < b->plan.n)
+        return fail(ASP_E_STATE, "decision scores not set for every instance");
+    hipStream_t s = (hipStream_t)stream;
+    DeviceInfo di = device_info();
+    int32_t rc = check_launch(b->plan, di);
+    if (rc) return rc;
+    const asp_limits L = lim ? *lim : asp_limits{-1, 0};
+    const size_t nc = b->plan.classes.size();
+    if (!b->ev0) {
+        HIPCHK(hipEventCreate(&b->ev0));
+        HIPCHK(hipEventCreate(&b->ev1));
+        HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    }
+    while (b->ev_cjoin.size() < nc) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->ev_cjoin.push_back(e);
+    }
+    while (nc > 1 && b->streams.size() < nc - 1) {
+        hipStream_t t;
+        HIPCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+        b->streams.push_back(t);
+    }
+    if (!b->gexec || b->gstream != s || b->glim.max_conflicts != L.max_conflicts ||
+        b->glim.max_ms != L.max_ms) {
+        if (b->gexec) {
+            HIPCHK(hipGraphExecDestroy(b->gexec));
+            b->gexec = nullptr;
+        }
+        // capture the same fork/join as the eager launch, without timing
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipEventRecord(b->ev_fork, s);
+        for (size_t c = 0; c < nc && e == hipSuccess; ++c) {
+            const LaunchClass& lc = b->plan.classes[c];
+            KArgs a = make_args(b->plan, b->arena, MODE_SOLVE, lc);
+            apply_limits(a, b->plan, &L, di);
+            hipStream_t cs = c == 0 ? s : b->streams[c - 1];
+            if (c > 0) e = hipStreamWaitEvent(cs, b->ev_fork, 0);
+            if (e == hipSuccess) e = launch_search(a, lc.threads, lc.count, lc.lds, cs);
+            if (e == hipSuccess && c > 0) e = hipEventRecord(b->ev_cjoin[c], cs);
+        }
+        for (size_t c = 1; c < nc && e == hipSuccess; ++c) e = hipStreamWaitEvent(s, b->ev_cjoin[c], 0);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (e != hipSuccess) return fail(ASP_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        if (e2 != hipSuccess) return fail(ASP_E_DEVICE, std::string("end capture: ") + hipGetErrorString(e2));
+        e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(ASP_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        b->gstream = s;
+        b->glim = L;
+    }
+    HIPCHK(hipEventRecord(b->ev0, s));
+    HIPCHK(hipGraphLaunch(b->gexec, s));
+    HIPCHK(hipEventRecord(b->ev1, s));
+    b->timed = true;
+    b->class_timed = false;
     return ASP_OK;
 }
 
@@ -1264,7 +1338,7 @@ int32_t asp_batch_launch_info(asp_batch* b, int32_t* n_classes, int32_t* first, 
         if (threads) threads[c] = P.classes[c].threads;
         if (ms) {
             ms[c] = 0.0;
-            if (b->timed && c < (int)b->ev_join.size()) {
+            if (b->class_timed && c < (int)b->ev_join.size()) {
                 HIPCHK(hipEventSynchronize(b->ev_join[c]));
                 float f = 0.f;
                 HIPCHK(hipEventElapsedTime(&f, b->ev_start[c], b->ev_join[c]));
@@ -1283,6 +1357,8 @@ int32_t asp_batch_free(asp_batch* b) {
         if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
         for (hipEvent_t e : b->ev_join) (void)hipEventDestroy(e);
         for (hipEvent_t e : b->ev_start) (void)hipEventDestroy(e);
+        for (hipEvent_t e : b->ev_cjoin) (void)hipEventDestroy(e);
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
         for (hipStream_t t : b->streams) (void)hipStreamDestroy(t);
         delete b;
     }

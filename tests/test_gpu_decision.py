@@ -177,3 +177,31 @@ def test_batch_scores_required(P):
                                  scores=aspgen.decision_scores(i, p.n_atoms))
         assert verd[i] == STATUS[rc]
         assert_same_stats(st, stats[i], i)
+
+
+def test_readout_training_matches_oracle(P):
+    """Device readout training (float32, atomics) against the oracle's
+    float64 Adam on the same last-layer codes and labels: losses to 1e-4
+    relative, weights to 1e-3 (float32 sums of a few thousand terms move a
+    gradient by ~1e-6 relative; Adam's normalised steps keep that small)."""
+    progs = [aspgen.tiny_program(s, 8, 20) for s in range(6)]
+    progs += [aspgen.single_random(1400 + s) for s in range(2)]
+    progs += [aspgen.batch_random(s, a_lo=100, a_hi=300) for s in range(2)]
+    w = aspgen.mpnn_weights(0)
+    rng = np.random.default_rng(5)
+    labels = [rng.integers(-1, 2, size=p.n_atoms).astype(np.int8) for p in progs]
+    gp = [P.Program(p) for p in progs]
+    b = P.Batch(gp).bind("cuda")
+    wb, loss = b.train_readout(w, np.concatenate(labels), steps=40, lr=0.05)
+    X, y = [], []
+    for p, lab in zip(progs, labels):
+        hv = mpnn.last_codes(w, mpnn.graph_of(p))
+        sel = np.nonzero(lab >= 0)[0]
+        X.append(hv[sel + 1] / 256.0)
+        y.append(lab[sel])
+    X = np.concatenate(X)
+    y = np.concatenate(y).astype(np.float64)
+    wr, lr_ = mpnn.train_readout(X, y, 40, 0.05)
+    assert np.allclose(loss, lr_, rtol=1e-4, atol=1e-6), (loss[:5], lr_[:5])
+    assert np.allclose(wb, wr, rtol=1e-3, atol=1e-3), np.abs(wb - wr).max()
+    assert loss[-1] < loss[0]

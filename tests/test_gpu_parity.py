@@ -242,3 +242,38 @@ def test_batch_parity_mixed(P, threads):
     verd2, models2, stats2 = b.results()
     untimed = lambda L: [{k: v for k, v in d.items() if not k.startswith("ns_")} for d in L]
     assert np.array_equal(verd, verd2) and untimed(stats) == untimed(stats2)
+
+
+def test_batch_graph_replays(P):
+    """The batched solve as a HIP graph: every replay, with eager device work
+    and synchronisations between replays, gives the eager launch's verdicts,
+    models and counters; changing the limits re-captures."""
+    import torch
+    progs = [aspgen.tiny_program(s, 4, 20) for s in range(20)]
+    progs += [aspgen.single_random(1500 + s) for s in range(3)]
+    progs += [aspgen.batch_random(s, a_lo=100, a_hi=400) for s in range(4)]
+    gp = [P.Program(p) for p in progs]
+    stream = torch.cuda.Stream()
+    b = P.Batch(gp, threads=128, classes=3)
+    with torch.cuda.stream(stream):
+        b.bind("cuda", stream=stream)
+    untimed = lambda L: [{k: v for k, v in d.items() if not k.startswith("ns_")} for d in L]
+    for budget in (200, 60):
+        lim = P.limits(budget, LIM_MS)
+        b.solve(lim)
+        torch.cuda.synchronize()
+        v0, m0, s0 = b.results()
+        for r in range(3):
+            x = torch.arange(1 << 20, device="cuda", dtype=torch.float32)
+            assert float((x * 2).sum()) > 0
+            torch.cuda.synchronize()
+            b.solve(lim, graph=True)
+            torch.cuda.synchronize()
+            v, m, st = b.results()
+            assert np.array_equal(v, v0), (budget, r)
+            assert all(np.array_equal(a, c) for a, c in zip(m, m0)), (budget, r)
+            assert untimed(st) == untimed(s0), (budget, r)
+        for i in (0, 21, 25):
+            rc, _, sto = oracle.solve(progs[i], limits=oracle.make_limits(budget))
+            assert v0[i] == STATUS[rc]
+            assert_same_stats(sto, s0[i], i)

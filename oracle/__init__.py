@@ -26,6 +26,7 @@ RUNNING, SAT, UNSAT, UNKNOWN = 0, 1, 2, 3
 E_INVALID, E_INTERNAL = -1, -5
 ST_NONE, ST_INIT, ST_ROUND, ST_LEARN, ST_DECIDE, ST_COMPLETE, ST_GATE, ST_DONE = range(8)
 GATE_UNFOUNDED, GATE_ALLDEC = 0, 1
+LEARN_FWD, LEARN_RES = 0, 1
 STEP_NAMES = {ST_INIT: "init", ST_ROUND: "round", ST_LEARN: "learn", ST_DECIDE: "decide",
               ST_COMPLETE: "complete", ST_GATE: "gate", ST_DONE: "done"}
 
@@ -93,7 +94,9 @@ def lib():
         L.or_model.argtypes = [P, np.ctypeslib.ndpointer(np.uint8, flags="C")]
         L.or_solve.argtypes = [C.c_int32, C.c_int32, i32p, i64p, i32p, C.c_int32, C.c_int32,
                                C.POINTER(Limits), np.ctypeslib.ndpointer(np.uint8, flags="C"),
-                               C.POINTER(Stats), C.c_void_p, C.c_int32]
+                               C.POINTER(Stats), C.c_void_p, C.c_int32, C.c_int32]
+        L.or_set_learning.argtypes = [P, C.c_int32]
+        L.or_set_learning.restype = C.c_int32
         L.or_set_scores.argtypes = [P, i32p, C.c_int32]
         L.or_set_scores.restype = C.c_int32
         L.or_score_mode.argtypes = [P, C.POINTER(C.c_int32)]
@@ -131,7 +134,7 @@ class State:
 class Solver:
     """One program in the oracle, steppable."""
 
-    def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED):
+    def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED, learning: int = LEARN_FWD):
         L = lib()
         err = C.c_int32(0)
         self._h = L.or_create(int(prog.n_atoms), int(prog.n_rules),
@@ -142,6 +145,8 @@ class Solver:
         if not self._h:
             raise ValueError(f"oracle rejected the program (status {err.value})")
         self.W = W
+        if L.or_set_learning(self._h, int(learning)) != 0:
+            raise ValueError("unknown learning mode")
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -219,7 +224,7 @@ class Solver:
 
 
 def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = None,
-          scores=None, fallback_after: int = 10):
+          scores=None, fallback_after: int = 10, learning: int = LEARN_FWD):
     """Encode and solve in one call; returns (status, model or None, stats).
     ``scores`` (int32[n_atoms + 1]) selects the score-driven Decision."""
     L = lib()
@@ -235,5 +240,6 @@ def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = 
                     np.ascontiguousarray(prog.body_off, np.int64),
                     np.ascontiguousarray(prog.body_lits, np.int32), int(W), int(gate),
                     C.byref(limits) if limits else None, m, C.byref(st),
-                    sc.ctypes.data if sc is not None else None, int(fallback_after))
+                    sc.ctypes.data if sc is not None else None, int(fallback_after),
+                    int(learning))
     return rc, (m[:A].copy() if rc == SAT else None), st.as_dict()

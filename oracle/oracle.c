@@ -17,9 +17,10 @@
  *               previous round's assignments are classified against one
  *               snapshot, the lowest-id implier wins a variable, clashing
  *               implications become conflicts.
- *   LEARN    -- Fwd-learning (Sect. 4.2, Alg. 4) from the Deps bitmaps, then
- *               Backjump (Alg. 1) and assertion of the complement of the most
- *               recent decision in the learned nogood.
+ *   LEARN    -- Fwd-learning (Sect. 4.2, Alg. 4) from the Deps bitmaps, or
+ *               (option) Res-learning (Alg. 3): resolution from the conflict
+ *               back to the first UIP; then Backjump (Alg. 1) and assertion
+ *               of the complement of the learned nogood's latest literal.
  *   DECIDE   -- the ASP-computation Decision (Sect. 2): among rules r whose
  *               head is unassigned with T t_r in A and F n_r not in A, pick the
  *               highest score of the head (ties: lowest rule) and assign T b_r
@@ -44,6 +45,13 @@
  *     F n_r, then follows by propagation);
  *   - CompleteAssignment's falsifications take level cdl and the Deps of all
  *     decisions;
+ *   - Res-learning orders assignments by an event clock (one tick per round,
+ *     decision, assertion, completion; the implications of a round share a
+ *     tick) and breaks ties by variable id; a literal's reason is the nogood
+ *     that implied it.  A round conflict whose resolution reaches a literal
+ *     with no reason at the conflict level (a CompleteAssignment literal), and
+ *     every stability-gate conflict, is learned by Fwd-learning instead; a
+ *     round conflict with no literal above level 1 means UNSAT;
  *   - supplied scores fall back to the occurrence heuristic, for the rest of
  *     the search, once `fallback_after` conflicts come in a row: the count
  *     grows at every conflict and restarts from zero whenever a decision's
@@ -58,6 +66,7 @@ enum { OR_E_INVALID = -1, OR_E_INTERNAL = -5 };
 enum { ST_NONE = 0, ST_INIT = 1, ST_ROUND = 2, ST_LEARN = 3, ST_DECIDE = 4,
        ST_COMPLETE = 5, ST_GATE = 6, ST_DONE = 7 };
 enum { GATE_UNFOUNDED = 0, GATE_ALLDEC = 1 };
+enum { LEARN_FWD = 0, LEARN_RES = 1 };
 
 typedef struct {
     int64_t rounds, visits, literal_checks, propagations, decisions, conflicts,
@@ -100,6 +109,12 @@ typedef struct {
     int32_t fallback_after;    /* <0: never fall back */
     int32_t consec;            /* conflicts since a decision reached a fixpoint */
     int32_t dec_since_conf;    /* a decision was taken since the last conflict */
+    int32_t learning;          /* LEARN_FWD or LEARN_RES */
+    int32_t clock;             /* assignment event clock (Res-learning order) */
+    int32_t *stamp;            /* [V+1] clock tick of each assignment */
+    int32_t *reason;           /* [V+1] nogood that implied it, -1 if none */
+    int32_t *mark;             /* [V+1] resolution membership (epoch) */
+    int32_t epoch;
 
     /* assignment */
     int8_t *val;
@@ -350,6 +365,10 @@ void *or_create(int32_t n_atoms, int32_t n_rules, const int32_t *head,
     s->winsign = (int8_t *)calloc(V1, 1);
     s->inM = (int8_t *)calloc((size_t)s->A + 1, 1);
     s->inLM = (int8_t *)calloc((size_t)s->A + 1, 1);
+    s->stamp = (int32_t *)calloc(V1, sizeof(int32_t));
+    s->reason = (int32_t *)malloc(V1 * sizeof(int32_t));
+    for (size_t v = 0; v < V1; ++v) s->reason[v] = -1;
+    s->mark = (int32_t *)calloc(V1, sizeof(int32_t));
     s->cdl = 1;
     s->st.trace_hash = 1469598103934665603ull;
     s->status = OR_RUNNING;
@@ -369,6 +388,7 @@ void or_free(void *h) {
     free(s->val); free(s->lvl); free(s->deps); free(s->tmpdeps); free(s->pend_B);
     free(s->dec); free(s->frontier.a); free(s->win); free(s->winsign); free(s->touched);
     free(s->inM); free(s->inLM);
+    free(s->stamp); free(s->reason); free(s->mark);
     free(s);
 }
 
@@ -390,6 +410,8 @@ static void step_init(or_solver *s) {
         if (s->val[x] == 0) {
             s->val[x] = want;
             s->lvl[x] = 1;
+            s->stamp[x] = s->clock;
+            s->reason[x] = (int32_t)id;
             s->nass += 1;
             iv_push(&s->frontier, x);
         } else if (s->val[x] != want) {
@@ -398,6 +420,7 @@ static void step_init(or_solver *s) {
         }
     }
     qsort(s->frontier.a, (size_t)s->frontier.n, sizeof(int32_t), cmp_i32);
+    s->clock += 1;
 }
 
 /* Classification of nogood id against the current assignment:
@@ -487,11 +510,14 @@ static void step_round(or_solver *s) {
         int32_t x = s->touched[i];
         s->val[x] = s->winsign[x];
         s->lvl[x] = s->cdl;
+        s->stamp[x] = s->clock;
+        s->reason[x] = s->win[x];
         memcpy(s->deps + (size_t)x * W, s->tmpdeps + (size_t)i * W, sizeof(uint64_t) * W);
     }
     for (int32_t i = 0; i < nt; ++i) s->win[s->touched[i]] = -1;
     s->frontier.n = 0;
     for (int32_t i = 0; i < nt; ++i) iv_push(&s->frontier, s->touched[i]);
+    s->clock += 1;
     s->nass += nt;
     s->st.rounds += 1;
     s->st.propagations += nt;
@@ -501,7 +527,73 @@ static void step_round(or_solver *s) {
     }
 }
 
-/* S6 + S7: Fwd-learning (Alg. 4) followed by Backjump and assertion. */
+static const or_solver *g_sort_s;   /* comparator context (single-threaded use) */
+static int cmp_assigned(const void *a, const void *b) {
+    const or_solver *s = g_sort_s;
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    if (s->stamp[x] != s->stamp[y]) return s->stamp[x] < s->stamp[y] ? -1 : 1;
+    return (x > y) - (x < y);
+}
+
+/* Res-learning (Alg. 3): starting from the conflict nogood (all its
+ * literals true), while the latest-assigned literal sigma shares its level
+ * with another literal, replace sigma by the other literals of the nogood
+ * that implied it.  On return the nogood has a single literal at its top
+ * level (the first UIP); *N holds its true literals by assignment order
+ * (sigma last) and *bj the highest level of the others (at least 1).
+ * Returns 0, leaving nothing allocated, when sigma has no implying nogood
+ * (a CompleteAssignment literal): the caller learns by Fwd-learning. */
+static int res_learn(or_solver *s, int32_t **outN, int64_t *outn, int32_t *outbj) {
+    s->epoch += 1;
+    const int32_t ep = s->epoch;
+    ivec d = {0};
+    const int32_t *L = ng_ptr(s, s->pend_id);
+    for (int32_t q = 0; q < ng_len(s, s->pend_id); ++q) {
+        int32_t v = var_of(L[q]);
+        if (s->mark[v] != ep) { s->mark[v] = ep; iv_push(&d, v); }
+    }
+    int32_t sig = -1, k = 0;
+    for (;;) {
+        sig = -1;
+        for (int64_t i = 0; i < d.n; ++i) {
+            int32_t v = d.a[i];
+            if (s->mark[v] != ep) continue;
+            if (sig < 0 || s->stamp[v] > s->stamp[sig] ||
+                (s->stamp[v] == s->stamp[sig] && v > sig)) sig = v;
+        }
+        k = 0;
+        for (int64_t i = 0; i < d.n; ++i) {
+            int32_t v = d.a[i];
+            if (s->mark[v] == ep && v != sig && s->lvl[v] > k) k = s->lvl[v];
+        }
+        if (s->lvl[sig] != k) break;
+        int32_t e = s->reason[sig];
+        if (e < 0) { free(d.a); return 0; }
+        s->mark[sig] = 0;                      /* resolve sigma away ... */
+        const int32_t *E = ng_ptr(s, e);
+        for (int32_t q = 0; q < ng_len(s, e); ++q) {   /* ... with its reason */
+            int32_t v = var_of(E[q]);
+            if (v == sig || s->mark[v] == ep) continue;
+            s->mark[v] = ep;
+            iv_push(&d, v);
+        }
+    }
+    int64_t n = 0;
+    for (int64_t i = 0; i < d.n; ++i)
+        if (s->mark[d.a[i]] == ep) d.a[n++] = d.a[i];
+    g_sort_s = s;
+    qsort(d.a, (size_t)n, sizeof(int32_t), cmp_assigned);
+    int32_t *N = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) N[i] = s->val[d.a[i]] > 0 ? d.a[i] : -d.a[i];
+    free(d.a);
+    *outN = N;
+    *outn = n;
+    *outbj = k > 1 ? k : 1;
+    return 1;
+}
+
+/* S6 + S7: Fwd-learning (Alg. 4) -- or Res-learning (Alg. 3) -- followed by
+ * Backjump and assertion. */
 static void step_learn(or_solver *s, const or_limits *lim) {
     const int32_t W = s->W;
     uint64_t *B = s->pend_B;
@@ -513,8 +605,15 @@ static void step_learn(or_solver *s, const or_limits *lim) {
             for (int32_t q = 0; q < W; ++q) B[q] |= s->deps[(size_t)y * W + q];
         }
     }
+    const int res = s->learning == LEARN_RES && s->pend_kind == 1;
     int zero = 1;
-    for (int32_t q = 0; q < W; ++q) zero &= B[q] == 0;
+    if (res) {
+        /* a round conflict with no literal above level 1 holds at the root */
+        const int32_t *L = ng_ptr(s, s->pend_id);
+        for (int32_t k = 0; k < ng_len(s, s->pend_id); ++k) zero &= s->lvl[var_of(L[k])] <= 1;
+    } else {
+        for (int32_t q = 0; q < W; ++q) zero &= B[q] == 0;
+    }
     if (zero) {
         /* the conflict follows from level-1 facts alone */
         s->st.conflicts += 1;
@@ -534,25 +633,39 @@ static void step_learn(or_solver *s, const or_limits *lim) {
             fnv(s, 7);
         }
     }
-    /* levels(B), ascending: level l in 2..64W-1 for bit l-1, plus every
-     * level 64W..cdl when the saturated bit 64W-1 is set */
-    ivec lev = {0};
-    for (int32_t l = 2; l <= s->cdl; ++l) {
-        int32_t b = level_bit(s, l);
-        if ((B[b / 64] >> (b % 64)) & 1u) iv_push(&lev, l);
+    int32_t *N = NULL, bj = 1;
+    int64_t nN = 0;
+    if (!(res && res_learn(s, &N, &nN, &bj))) {
+        /* levels(B), ascending: level l in 2..64W-1 for bit l-1, plus every
+         * level 64W..cdl when the saturated bit 64W-1 is set */
+        if (res) {
+            /* Res-learning fell back: the Deps of the conflict give B */
+            memset(B, 0, sizeof(uint64_t) * W);
+            const int32_t *L = ng_ptr(s, s->pend_id);
+            for (int32_t k = 0; k < ng_len(s, s->pend_id); ++k) {
+                int32_t y = var_of(L[k]);
+                for (int32_t q = 0; q < W; ++q) B[q] |= s->deps[(size_t)y * W + q];
+            }
+        }
+        ivec lev = {0};
+        for (int32_t l = 2; l <= s->cdl; ++l) {
+            int32_t b = level_bit(s, l);
+            if ((B[b / 64] >> (b % 64)) & 1u) iv_push(&lev, l);
+        }
+        nN = lev.n;
+        N = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nN > 0 ? nN : 1));
+        for (int64_t i = 0; i < nN; ++i) N[i] = s->dec[lev.a[i]];
+        bj = nN >= 2 ? lev.a[nN - 2] : 1;
+        free(lev.a);
     }
-    int64_t nN = lev.n;
     if ((lim && lim->learned_cap_ng >= 0 && s->n_learned + 1 > lim->learned_cap_ng) ||
         (lim && lim->learned_cap_lits >= 0 && s->learned_lits + nN > lim->learned_cap_lits)) {
-        free(lev.a);
+        free(N);
         s->status = OR_UNKNOWN;
         return;
     }
-    int32_t *N = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nN > 0 ? nN : 1));
-    for (int64_t i = 0; i < nN; ++i) N[i] = s->dec[lev.a[i]];
-    int32_t topl = lev.a[nN - 1];
-    int32_t bj = nN >= 2 ? lev.a[nN - 2] : 1;
-    int32_t toplit = s->dec[topl];
+    int32_t toplit = N[nN - 1];
+    const int32_t newid = (int32_t)(s->n0 + s->n_learned);
     add_nogood(s, N, (int32_t)nN);
     s->n_learned += 1;
     s->learned_lits += nN;
@@ -573,6 +686,8 @@ static void step_learn(or_solver *s, const or_limits *lim) {
     s->nass += 1;
     s->val[x] = (int8_t)-lit_sign(toplit);
     s->lvl[x] = bj;
+    s->stamp[x] = s->clock++;
+    s->reason[x] = newid;
     uint64_t *d = s->deps + (size_t)x * W;
     memset(d, 0, sizeof(uint64_t) * W);
     for (int64_t i = 0; i + 1 < nN; ++i) {
@@ -584,7 +699,6 @@ static void step_learn(or_solver *s, const or_limits *lim) {
     s->pend_kind = 0;
     s->pend_id = -1;
     free(N);
-    free(lev.a);
 }
 
 /* S8: pick an applicable rule (T t_r in A, F n_r not in A, head unassigned)
@@ -617,6 +731,8 @@ static void step_decide(or_solver *s, int32_t j) {
     s->nass += 1;
     s->val[b] = 1;
     s->lvl[b] = s->cdl;
+    s->stamp[b] = s->clock++;
+    s->reason[b] = -1;
     uint64_t *d = s->deps + (size_t)b * W;
     memset(d, 0, sizeof(uint64_t) * W);
     int32_t bit = level_bit(s, s->cdl);
@@ -638,6 +754,8 @@ static void step_complete(or_solver *s) {
         s->val[p] = -1;
         s->nass += 1;
         s->lvl[p] = s->cdl;
+        s->stamp[p] = s->clock;
+        s->reason[p] = -1;
         uint64_t *d = s->deps + (size_t)p * W;
         memset(d, 0, sizeof(uint64_t) * W);
         for (int32_t l = 2; l <= s->cdl; ++l) {
@@ -646,6 +764,7 @@ static void step_complete(or_solver *s) {
         }
         iv_push(&s->frontier, p);
     }
+    s->clock += 1;
     s->st.completes += 1;
     fnv(s, 3); fnv(s, (int32_t)s->frontier.n);
     if (s->frontier.n == 0) s->status = OR_E_INTERNAL;
@@ -778,6 +897,15 @@ int32_t or_set_scores(void *h, const int32_t *score, int32_t fallback_after) {
     return 0;
 }
 
+/* Choose the Learning step (LEARN_FWD, LEARN_RES) before the first step.
+ * Returns 0, or OR_E_INVALID. */
+int32_t or_set_learning(void *h, int32_t mode) {
+    or_solver *s = (or_solver *)h;
+    if (s->last_step != ST_NONE || (mode != LEARN_FWD && mode != LEARN_RES)) return OR_E_INVALID;
+    s->learning = mode;
+    return 0;
+}
+
 /* 1 while the supplied scores drive Decision, 0 after the fallback (or when
  * none were supplied); *consec gets the current run of conflicts */
 int32_t or_score_mode(void *h, int32_t *consec) {
@@ -816,11 +944,13 @@ void or_model(void *h, uint8_t *model) {
 int32_t or_solve(int32_t n_atoms, int32_t n_rules, const int32_t *head,
                  const int64_t *body_off, const int32_t *body_lits, int32_t W,
                  int32_t gate_mode, const or_limits *lim, uint8_t *model,
-                 or_stats *st, const int32_t *score, int32_t fallback_after) {
+                 or_stats *st, const int32_t *score, int32_t fallback_after,
+                 int32_t learning) {
     int32_t err = 0;
     void *h = or_create(n_atoms, n_rules, head, body_off, body_lits, W, gate_mode, &err);
     if (!h) return err;
     if (score) or_set_scores(h, score, fallback_after);
+    if (or_set_learning(h, learning) != 0) { or_free(h); return OR_E_INVALID; }
     int32_t rc = or_run(h, lim, -1);
     if (model && rc == OR_SAT) or_model(h, model);
     if (st) or_get_stats(h, st);

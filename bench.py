@@ -216,6 +216,19 @@ def time_split(stats, members=None):
     return out
 
 
+def search_counters(stats, ms_step):
+    """Per-second search counters of a whole step (the quantities the
+    paper's Fig. 1 and Fig. 2 compare between Fwd- and Res-learning)."""
+    tot = {k: sum(int(s[k]) for s in stats)
+           for k in ("propagations", "decisions", "conflicts", "learned", "learned_len")}
+    sec = ms_step / 1000.0
+    return {"propagations_per_s": tot["propagations"] / sec,
+            "decisions_per_s": tot["decisions"] / sec,
+            "conflicts_per_s": tot["conflicts"] / sec,
+            "learned_per_s": tot["learned"] / sec,
+            "avg_learned_len": tot["learned_len"] / max(tot["learned"], 1)}
+
+
 def verify_models(progs, verd, models):
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from judge import is_stable
@@ -243,6 +256,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-steps", type=int, default=2)
+    ap.add_argument("--no-res", action="store_true", help="skip the Res-learning leg")
+    ap.add_argument("--res-steps", type=int, default=2)
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="replays of the batched solve as one HIP graph, timed after the eager steps")
     ap.add_argument("--autotune", action="store_true",
@@ -361,6 +376,7 @@ def main():
         "launch_ms": [c[3] for c in info],
         "instance_ms": tl,
         "time_split": {"all": split_all, "dominant_launch": split_dom},
+        "counters": search_counters(stats, ms_step),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": tb,
                      "launch": f"LDS class {dom}: {count} instances, {thr} threads, "
@@ -382,6 +398,9 @@ def main():
         line["graph"] = {"ms_per_step": float(np.mean(gms[1:])), "replays": args.graph_steps,
                          "same_results_as_eager": bool(same)}
 
+    if not args.no_res:
+        log("[bench] Res-learning leg")
+        line["res"] = res_leg(args, P, progs, verd, stream, dev, lim, ms_step, cth)
     if not args.no_learned:
         log("[bench] learned Decision leg")
         line["learned"] = learned_leg(args, P, progs, verd, stream, dev, lim, ms_step, cth)
@@ -390,6 +409,41 @@ def main():
         line["cpu_baseline"] = cpu_baseline(progs, args.W, args.budget, args.cap_ng,
                                             args.cap_lits, args.cpu_seconds, stats)
     print(json.dumps(line), flush=True)
+
+
+def res_leg(args, P, progs, fwd_verd, stream, dev, lim, fwd_ms_step, cth):
+    """The same batch, budget and schedule with Res-learning (Alg. 3) in
+    place of Fwd-learning."""
+    import torch
+    gp = load_programs(progs, args.W, args.cap_ng, args.cap_lits, learning=P.LEARN_RES)
+    batch = P.Batch(gp, threads=args.threads, classes=args.classes, class_threads=cth)
+    with torch.cuda.stream(stream):
+        batch.bind(dev, stream=stream)
+    torch.cuda.synchronize()
+    ms, walls = timed_steps(batch, lim, args.res_steps, 1)
+    verd, models, stats = batch.results()
+    n_sat = int((verd == 1).sum())
+    n_unsat = int((verd == 2).sum())
+    ms_step = float(np.sum(walls)) * 1000.0 / len(walls)
+    contra = int(((verd == 1) & (fwd_verd == 2)).sum() + ((verd == 2) & (fwd_verd == 1)).sum())
+    n_sat_checked, bad = verify_models(progs, verd, models)
+    ips = (n_sat + n_unsat) / (ms_step / 1000.0)
+    fwd_ips = int(((fwd_verd == 1) | (fwd_verd == 2)).sum()) / (fwd_ms_step / 1000.0)
+    out = {
+        "ms_per_step": ms_step, "instances_per_s": ips,
+        "vs_fwd_instances_per_s": ips / fwd_ips if fwd_ips > 0 else None,
+        "verdicts": {"sat": n_sat, "unsat": n_unsat, "unknown": int((verd == 3).sum()),
+                     "error": int((verd < 0).sum())},
+        "verdict_contradictions_vs_fwd": contra,
+        "models_verified": {"sat": n_sat_checked, "not_stable": len(bad)},
+        "literal_checks_per_s": sum(int(s["literal_checks"]) for s in stats) / (ms_step / 1000.0),
+        "counters": search_counters(stats, ms_step),
+        "time_split": time_split(stats),
+        "instance_ms": tail(stats),
+    }
+    del batch
+    torch.cuda.empty_cache()
+    return out
 
 
 def learned_leg(args, P, progs, plain_verd, stream, dev, lim, plain_ms_step, cth):

@@ -70,6 +70,12 @@ extern "C" {
 
 /* Decision heuristics (Sect. 2, the ASP-computation Decision: an applicable
  * rule is chosen by a score of its head, ties to the lowest rule). */
+#define ASP_LEARN_FWD      0  /* Fwd-learning from Deps bitmaps (Sect. 4.2, Alg. 4) */
+#define ASP_LEARN_RES      1  /* Res-learning: resolution to the first UIP (Alg. 3);
+                                 stability-gate conflicts, and resolutions that
+                                 reach a CompleteAssignment literal, use
+                                 Fwd-learning */
+
 #define ASP_DECISION_OCC   0  /* occurrences of the head in Delta_0 */
 #define ASP_DECISION_SCORE 1  /* per-atom integer scores set on the device
                                  (asp_set_scores, or the learned scorer of
@@ -95,6 +101,8 @@ typedef struct {
                                   conflict-free fixpoint) the occurrence
                                   heuristic takes over for the rest of the
                                   search; < 0 never.  Default 10 */
+    int32_t learning;          /* ASP_LEARN_FWD (default) or ASP_LEARN_RES */
+    int32_t reserved;
 } asp_options;
 
 /* Run limits. */
@@ -185,7 +193,8 @@ typedef struct {
  *  body_off   : n_rules+1 offsets, non-decreasing, body_off[0] = 0
  *  body_lits  : +a (atom a) or -a (not a), 1 <= a <= n_atoms
  *  opt        : NULL = {W=1, gate=UNFOUNDED, learned_cap_ng=1<<20,
- *               learned_cap_lits=1<<22, decision=OCC, fallback_after=10}
+ *               learned_cap_lits=1<<22, decision=OCC, fallback_after=10,
+ *               learning=FWD}
  * Repeated body literals are removed (first kept); a constraint holding both
  * a and not a is dropped.  Nogoods are generated per headed rule, then per
  * atom, then per constraint, and stably sorted by length (Sect. 4); their
@@ -258,8 +267,9 @@ int32_t asp_solve(asp_program *prog, void *stream, const asp_limits *lim,
 int32_t asp_state_export(asp_program *prog, void *stream, asp_state *st);
 
 /* State import (the frontier must hold variables of level cdl; the pending
- * field may name a round conflict).  Errors: ASP_E_INVALID on inconsistent
- * input, ASP_E_CAPACITY beyond the learned-store capacity. */
+ * field may name a round conflict; learned nogoods must hold decision
+ * literals T b_r only).  Fwd-learning programs only.  Errors: ASP_E_INVALID
+ * on inconsistent input, ASP_E_CAPACITY beyond the learned-store capacity. */
 int32_t asp_state_import(asp_program *prog, void *stream, const asp_state *st);
 
 /* ------------------------------------------------------------ batches */

@@ -20,6 +20,7 @@ E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_INTERNAL, E_TIMEOUT = -1, -2, -3, -4
 STEP_NONE, STEP_INIT, STEP_ROUND, STEP_LEARN, STEP_DECIDE, STEP_COMPLETE, STEP_GATE, STEP_DONE = range(8)
 GATE_UNFOUNDED, GATE_ALLDEC = 0, 1
 DECISION_OCC, DECISION_SCORE = 0, 1
+LEARN_FWD, LEARN_RES = 0, 1
 SCORER_F, SCORER_H, SCORER_L = 8, 64, 3
 
 
@@ -32,7 +33,7 @@ class AspError(RuntimeError):
 class asp_options(C.Structure):
     _fields_ = [("W", C.c_int32), ("gate", C.c_int32), ("learned_cap_ng", C.c_int64),
                 ("learned_cap_lits", C.c_int64), ("decision", C.c_int32),
-                ("fallback_after", C.c_int32)]
+                ("fallback_after", C.c_int32), ("learning", C.c_int32), ("reserved", C.c_int32)]
 
 
 class asp_limits(C.Structure):
@@ -224,9 +225,9 @@ def limits(max_conflicts: int = -1, max_ms: int = 0) -> asp_limits:
 
 def options(W: int = 1, gate: int = GATE_UNFOUNDED, learned_cap_ng: int = 1 << 20,
             learned_cap_lits: int = 1 << 22, decision: int = DECISION_OCC,
-            fallback_after: int = 10) -> asp_options:
+            fallback_after: int = 10, learning: int = LEARN_FWD) -> asp_options:
     return asp_options(int(W), int(gate), int(learned_cap_ng), int(learned_cap_lits),
-                       int(decision), int(fallback_after))
+                       int(decision), int(fallback_after), int(learning), 0)
 
 
 @dataclass
@@ -255,11 +256,13 @@ class Program:
 
     def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED,
                  learned_cap_ng: int = 1 << 20, learned_cap_lits: int = 1 << 22,
-                 decision: int = DECISION_OCC, fallback_after: int = 10):
+                 decision: int = DECISION_OCC, fallback_after: int = 10,
+                 learning: int = LEARN_FWD):
         self._head = np.ascontiguousarray(prog.head, np.int32)
         self._off = np.ascontiguousarray(prog.body_off, np.int64)
         self._lits = np.ascontiguousarray(prog.body_lits, np.int32)
-        self.opt = options(W, gate, learned_cap_ng, learned_cap_lits, decision, fallback_after)
+        self.opt = options(W, gate, learned_cap_ng, learned_cap_lits, decision, fallback_after,
+                           learning)
         self.sizes = asp_sizes()
         h = C.c_void_p()
         _check(lib().asp_load_program(int(prog.n_atoms), int(self._head.shape[0]),

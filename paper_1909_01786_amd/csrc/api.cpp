@@ -85,7 +85,7 @@ struct LaunchClass {
 };
 
 struct Plan {
-    int32_t n = 0, threads = 256, W = 1, gate = 0, decision = 0, fallback_after = 10;
+    int32_t n = 0, threads = 256, W = 1, gate = 0, decision = 0, fallback_after = 10, learning = 0;
     int64_t Vmax = 0, Rhmax = 0, cap_ng = 0, cap_lits = 0;
     std::vector<LaunchClass> classes;
     std::vector<InstDesc> desc;
@@ -165,6 +165,7 @@ asp_options default_options() {
     o.learned_cap_lits = 1 << 22;
     o.decision = ASP_DECISION_OCC;
     o.fallback_after = 10;
+    o.learning = ASP_LEARN_FWD;
     return o;
 }
 
@@ -188,6 +189,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.gate = opt.gate;
     P.decision = opt.decision;
     P.fallback_after = opt.fallback_after;
+    P.learning = opt.learning;
     P.cap_ng = opt.learned_cap_ng;
     P.cap_lits = opt.learned_cap_lits;
     P.desc.resize(P.n);
@@ -226,7 +228,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
         P.Vmax = std::max<int64_t>(P.Vmax, h.V);
         P.Rhmax = std::max<int64_t>(P.Rhmax, h.Rh);
         P.slot_off[i] = P.slots_bytes;
-        P.slots_bytes += slot_layout(h.V, h.Rh, P.W, P.cap_ng, P.cap_lits).stride;
+        P.slots_bytes += slot_layout(h.V, h.Rh, P.W, P.cap_ng, P.cap_lits, P.learning).stride;
     }
     // launch classes by variable count; largest first inside a class
     const std::vector<int64_t> bounds = class_bounds(std::max(1, n_classes));
@@ -348,6 +350,7 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& 
     a.gate_mode = P.gate;
     a.decision = P.decision;
     a.fallback_after = P.fallback_after;
+    a.learning = P.learning;
     a.words = lc.words;
     a.step_mask = 0;
     a.max_steps = -1;
@@ -441,7 +444,8 @@ int32_t run_single(asp_program* p, hipStream_t s, int32_t mode, int32_t mask, in
 
 // the single program's slot (instance 0)
 SlotLayout slot0(const asp_program* p) {
-    return slot_layout(p->hp.V, p->hp.Rh, p->opt.W, p->opt.learned_cap_ng, p->opt.learned_cap_lits);
+    return slot_layout(p->hp.V, p->hp.Rh, p->opt.W, p->opt.learned_cap_ng, p->opt.learned_cap_lits,
+                       p->opt.learning);
 }
 
 SlotCtrl* ctrl_ptr(asp_program* p) { return (SlotCtrl*)(p->arena + p->plan.off_slots + slot0(p).ctrl); }
@@ -668,6 +672,8 @@ int32_t asp_load_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
         return fail(ASP_E_INVALID, "learned capacities must be in 1..2^29");
     if (o.decision != ASP_DECISION_OCC && o.decision != ASP_DECISION_SCORE)
         return fail(ASP_E_INVALID, "unknown decision heuristic");
+    if (o.learning != ASP_LEARN_FWD && o.learning != ASP_LEARN_RES)
+        return fail(ASP_E_INVALID, "unknown learning step");
     std::unique_ptr<asp_program> p(new asp_program());
     std::string err;
     int rc = encode_program(n_atoms, n_rules, head, body_off, body_lits, &p->hp, &err);
@@ -909,6 +915,9 @@ int32_t asp_state_export(asp_program* p, void* stream, asp_state* st) {
 
 int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
     if (!p || !p->bound || !st) return fail(ASP_E_STATE, "program not bound or null state");
+    if (p->opt.learning != ASP_LEARN_FWD)
+        return fail(ASP_E_INVALID, "state import needs assignment stamps and reasons that "
+                                   "Res-learning programs keep on the device only");
     const int32_t V = p->hp.V, W = p->opt.W, A = p->hp.A, Rh = p->hp.Rh;
     const int32_t nS = (int32_t)p->hp.n_nogoods();
     if (st->n_vars != V || st->W != W) return fail(ASP_E_INVALID, "state shape mismatch");
@@ -1068,7 +1077,7 @@ int32_t asp_batch_create(int32_t n, asp_program* const* progs, const asp_schedul
         const asp_options& o = progs[i]->opt;
         if (o.W != b->opt.W || o.gate != b->opt.gate || o.learned_cap_ng != b->opt.learned_cap_ng ||
             o.learned_cap_lits != b->opt.learned_cap_lits || o.decision != b->opt.decision ||
-            o.fallback_after != b->opt.fallback_after)
+            o.fallback_after != b->opt.fallback_after || o.learning != b->opt.learning)
             return fail(ASP_E_INVALID, "batch programs must share their options");
         b->progs.push_back(&progs[i]->hp);
     }

@@ -53,7 +53,8 @@ struct SlotCtrl {
     int32_t inst, cdl, qh, qt;
     int32_t n_learned, pool_top, pending, pend_kind;  // pend_kind 0 none, 1 round, 2 gate
     int32_t status, init_done, last_step, use_score;
-    int32_t consec, dec_open, pad1, pad2;    // learned-Decision fallback state
+    int32_t consec, dec_open;                // learned-Decision fallback state
+    int32_t clock, epoch;                    // assignment clock, resolution marks
     int64_t learned_lits;
     int64_t rounds, visits, checks, props, decisions, conflicts, learned, learned_len,
             gate_fail, completes;
@@ -77,15 +78,21 @@ struct SlotLayout {
     int64_t l_off;      // int32[cap_ng+1]
     int64_t l_lits;     // int32[cap_lits]
     int64_t pool;       // int32[pool_cap]
+    int64_t stamp;      // int32[V+1] assignment clock tick (Res-learning order)
+    int64_t reason;     // int32[V+1] nogood that implied the assignment, -1 none
+    int64_t mark;       // int32[V+1] resolution membership (epoch)
+    int64_t resd;       // int32[V+1] variables of the nogood being resolved
     int64_t stride;     // bytes of the slot
     int64_t pool_cap;   // entries
 };
 
-// Slot of an instance with V variables and Rh headed rules.  The learned
-// nogoods hold only decision literals T b_r, so at most Rh occurrence lists
-// exist; a doubling list of n entries has used at most 4n + 8 pool entries.
+// Slot of an instance with V variables and Rh headed rules.  A doubling
+// list of n entries has used at most 4n + 8 pool entries.  Fwd-learning
+// learns decision literals T b_r only, so at most Rh occurrence lists exist;
+// Res-learning may learn any literal (at most min(cap_lits, 2(V+1)) lists).
 __host__ __device__ inline SlotLayout slot_layout(int64_t V, int64_t Rh, int32_t W,
-                                                  int64_t cap_ng, int64_t cap_lits) {
+                                                  int64_t cap_ng, int64_t cap_lits,
+                                                  int32_t learning) {
     SlotLayout L;
     int64_t o = 0;
     const int64_t V1 = V + 1, R3 = Rh + 3;
@@ -103,8 +110,13 @@ __host__ __device__ inline SlotLayout slot_layout(int64_t V, int64_t Rh, int32_t
     ASP_TAKE(locc_cap, 8 * V1);
     ASP_TAKE(l_off, 4 * (cap_ng + 1));
     ASP_TAKE(l_lits, 4 * cap_lits);
-    L.pool_cap = 4 * cap_lits + 8 * (Rh + 1);
+    const int64_t lists = learning ? (cap_lits < 2 * V1 ? cap_lits : 2 * V1) : Rh + 1;
+    L.pool_cap = 4 * cap_lits + 8 * lists;
     ASP_TAKE(pool, 4 * L.pool_cap);
+    ASP_TAKE(stamp, 4 * V1);
+    ASP_TAKE(reason, 4 * V1);
+    ASP_TAKE(mark, 4 * V1);
+    ASP_TAKE(resd, 4 * V1);
 #undef ASP_TAKE
     L.stride = o;
     return L;
@@ -124,6 +136,7 @@ enum StepKind : int32_t {
 };
 
 enum Decision : int32_t { DECISION_OCC = 0, DECISION_SCORE = 1 };
+enum Learning : int32_t { LEARN_FWD = 0, LEARN_RES = 1 };
 
 enum Mode : int32_t {
     MODE_SOLVE = 0,      // workgroup b solves instance order[first + b] to a verdict
@@ -160,6 +173,8 @@ struct KArgs {
     int32_t W, gate_mode;
     int32_t decision;            // DECISION_OCC or DECISION_SCORE
     int32_t fallback_after;      // conflicts in a row before scores give way; <0 never
+    int32_t learning;            // LEARN_FWD or LEARN_RES
+    int32_t pad1;
     int32_t words;               // LDS words per 2-bit map (this launch's largest V)
     int32_t step_mask;           // MODE_STEPS: kinds allowed to run (bit k)
     int64_t max_steps;           // MODE_STEPS: steps to run; MODE_SOLVE: guard

@@ -61,6 +61,7 @@ struct Ctl {
     int32_t cdl, qh, qt, n_learned, pend_kind, pending, status, init_done, last_step, pool_top;
     int32_t use_score, consec, dec_open;   // score-driven Decision and its fallback
     int32_t fr_ok;    // the LDS records describe the frontier trail[qh..qt)
+    int32_t clock, epoch;   // assignment clock and resolution-mark epoch (Res-learning)
     int64_t learned_lits, rounds, props, decisions, conflicts, learned, learned_len, gate_fail,
             completes, steps, visits, checks;
     uint64_t hash;
@@ -86,6 +87,7 @@ struct Ctx {
     SlotCtrl* ctrl;
     int8_t* val8;
     int32_t *lvl, *trail, *tlim, *dec, *lptr, *ln, *lcap, *loff, *llits, *pool;
+    int32_t *stamp, *reason, *mark, *resd;
     unsigned long long* win;
     uint64_t* deps;
     int64_t pool_cap;
@@ -109,7 +111,7 @@ struct Ctx {
     unsigned long long* sB;
     Scr* scr;
     int32_t W, T, tid, lane, wid, nw;
-    int32_t decision, fallback_after;
+    int32_t decision, fallback_after, learning;
     unsigned long long my_visits, my_checks;
 };
 
@@ -292,7 +294,7 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     k.u0 = uni(d.u0);
     k.u1 = uni(d.u1);
     k.has_empty = uni(d.has_empty);
-    const SlotLayout lay = slot_layout(k.V, k.Rh, a.W, a.cap_ng, a.cap_lits);
+    const SlotLayout lay = slot_layout(k.V, k.Rh, a.W, a.cap_ng, a.cap_lits, a.learning);
     uint8_t* slot = a.slots + a.slot_off[inst];
     c.NO = a.ng_off + d.ng_off;
     c.NL = a.ng_lits + d.ng_lits;
@@ -317,6 +319,10 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     c.loff = (int32_t*)(slot + lay.l_off);
     c.llits = (int32_t*)(slot + lay.l_lits);
     c.pool = (int32_t*)(slot + lay.pool);
+    c.stamp = (int32_t*)(slot + lay.stamp);
+    c.reason = (int32_t*)(slot + lay.reason);
+    c.mark = (int32_t*)(slot + lay.mark);
+    c.resd = (int32_t*)(slot + lay.resd);
     c.pool_cap = lay.pool_cap;
 }
 
@@ -332,6 +338,7 @@ DEV void reset_search(Ctx& c, Ctl& k) {
         c.lvl[v] = 0;
         c.val8[v] = 0;
         st_wg(&c.win[v], WIN_NONE);
+        c.mark[v] = 0;
     }
     for (int q = tid; q < (V + 1) * W; q += T) c.deps[q] = 0ull;
     for (int q = tid; q < 2 * (V + 1); q += T) {
@@ -361,6 +368,7 @@ DEV void reset_search(Ctx& c, Ctl& k) {
     k.dec_open = 0;
     k.t_round = k.t_learn = k.t_decide = k.t_gate = 0;
     k.fr_ok = 0;
+    k.clock = k.epoch = 0;
     tab_clear_all(c);
     bar();
 }
@@ -407,6 +415,8 @@ DEV void load_ctrl(Ctx& c, Ctl& k) {
     k.use_score = uni(g.use_score);
     k.consec = uni(g.consec);
     k.dec_open = uni(g.dec_open);
+    k.clock = uni(g.clock);
+    k.epoch = uni(g.epoch);
     k.steps = 0;
     k.t_round = k.t_learn = k.t_decide = k.t_gate = 0;
     k.fr_ok = 0;
@@ -457,6 +467,8 @@ DEV void save_ctrl(Ctx& c, const Ctl& k) {
     g.use_score = k.use_score;
     g.consec = k.consec;
     g.dec_open = k.dec_open;
+    g.clock = k.clock;
+    g.epoch = k.epoch;
     bar();
 }
 
@@ -494,6 +506,8 @@ DEV void step_init(Ctx& c, Ctl& k) {
             uint32_t code = vget(c.pendb, x);
             vset(c.valb, x, code);
             c.lvl[x] = 1;
+            c.stamp[x] = k.clock;
+            c.reason[x] = -1;    // never resolved: conflicts at level 1 mean UNSAT
         }
     }
     bar();
@@ -505,6 +519,7 @@ DEV void step_init(Ctx& c, Ctl& k) {
     } else {
         k.qh = q0;
         k.qt = q1;
+        k.clock += 1;
     }
     k.fr_ok = 0;
 }
@@ -586,8 +601,9 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
             // makes true, kept in a slot in case this implier wins
             // (the map literal's variable is the frontier variable: its Deps
             // come with the frontier; a short nogood's entry holds the map
-            // segment of each literal it can make true; learned occurrence
-            // lists exist only for decision literals T b_r)
+            // segment of each literal it can make true; under Fwd-learning
+            // learned occurrence lists exist only for decision literals T b_r,
+            // under Res-learning for literals of either sign)
             unsigned long long d;
             int s0, cs;
             if (inl) {
@@ -606,9 +622,11 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
                 s0 = c.MO[li];
                 cs = c.MO[li + 1] - s0;
             }
-            const bool dec_lit = code == VT && x > k.A && (x - k.A - 1) % 3 == 0;
-            const int l0 = dec_lit ? c.lptr[2 * x] : 0;
-            const int cl = dec_lit ? c.ln[2 * x] : 0;
+            const bool dec_lit = c.learning == LEARN_RES ||
+                                 (code == VT && x > k.A && (x - k.A - 1) % 3 == 0);
+            const int lli = 2 * x + (code == VF ? 1 : 0);
+            const int l0 = dec_lit ? c.lptr[lli] : 0;
+            const int cl = dec_lit ? c.ln[lli] : 0;
             const int sl = atomicAdd(&c.scr->nimpl, 1);
             if (sl < kImplCap) {
                 c.iDeps[sl] = d;
@@ -795,6 +813,8 @@ DEV void step_round(Ctx& c, Ctl& k) {
             if (rec) put_record(c, i - qt, x, code, dx[0]);
         }
         c.lvl[x] = cdl;
+        c.stamp[x] = k.clock;
+        c.reason[x] = id;
         vset(c.valb, x, code);
         vclr(c.pendb, x);
     }
@@ -816,6 +836,7 @@ DEV void step_round(Ctx& c, Ctl& k) {
     k.qh = qt;
     k.qt = nt;
     k.fr_ok = rec ? 1 : 0;
+    k.clock += 1;
     k.rounds += 1;
     k.props += nt - qt;
     if (ck != ~0ull) {
@@ -824,7 +845,92 @@ DEV void step_round(Ctx& c, Ctl& k) {
     }
 }
 
-// Fwd-learning (Sect. 4.2, Alg. 4) + Backjump + assertion.
+// Res-learning (Alg. 3) of the pending round conflict: while the literal
+// assigned last (clock tick, then variable) shares its level with another
+// literal, resolve it away with the nogood that implied it.  Writes the
+// first-UIP nogood's true literals by assignment order (the UIP last) to
+// the learned store at `base`.  Returns 1, or 0 when the literal to resolve
+// has no implying nogood (a CompleteAssignment literal; the caller learns
+// by Fwd-learning), or -1 when the learned store is full.
+DEV int res_learn(Ctx& c, Ctl& k, const KArgs& a, int base, int* nN_out, int* bj_out) {
+    const int T = c.T, tid = c.tid;
+    const int ep = k.epoch + 1;
+    k.epoch = ep;
+    const int32_t* lits;
+    int len;
+    ng_span(c, k, k.pending, lits, len);
+    for (int q = tid; q < len; q += T) {
+        const int v = lvar(lits[q]);
+        c.mark[v] = ep;
+        c.resd[q] = v;
+    }
+    int n = len, kk = 0;
+    bar();
+    for (;;) {
+        unsigned long long best = 0ull;
+        for (int i = tid; i < n; i += T) {
+            const int v = c.resd[i];
+            if (c.mark[v] == ep) {
+                const unsigned long long key = ((unsigned long long)(uint32_t)c.stamp[v] << 32) | (uint32_t)v;
+                best = key > best ? key : best;
+            }
+        }
+        const int sig = (int)(uint32_t)(block_max_u64(c, best) & 0xffffffffull);
+        unsigned long long mk = 0ull;
+        for (int i = tid; i < n; i += T) {
+            const int v = c.resd[i];
+            if (c.mark[v] == ep && v != sig) {
+                const unsigned long long l = (unsigned long long)c.lvl[v];
+                mk = l > mk ? l : mk;
+            }
+        }
+        kk = (int)block_max_u64(c, mk);
+        if (uni(c.lvl[sig]) != kk) break;
+        const int e = uni(c.reason[sig]);
+        if (e < 0) return 0;
+        // resolve sigma away with its reason: add the reason's other variables
+        c.scr->tail = 0;
+        c.mark[sig] = 0;                       // identical from every lane
+        bar();
+        const int32_t* E;
+        int elen;
+        ng_span(c, k, e, E, elen);
+        for (int q = tid; q < elen; q += T) {
+            const int v = lvar(E[q]);
+            if (v != sig && c.mark[v] != ep) {
+                c.mark[v] = ep;
+                c.resd[n + atomicAdd(&c.scr->tail, 1)] = v;
+            }
+        }
+        bar();
+        n += uni(c.scr->tail);
+    }
+    // the live variables in assignment order
+    unsigned long long m = 0ull;
+    for (int i = tid; i < n; i += T) m += c.mark[c.resd[i]] == ep ? 1ull : 0ull;
+    const int nN = (int)block_sum_u64(c, m);
+    if (k.n_learned + 1 > a.cap_ng || k.learned_lits + nN > a.cap_lits) return -1;
+    for (int i = tid; i < n; i += T) {
+        const int v = c.resd[i];
+        if (c.mark[v] != ep) continue;
+        const unsigned long long kv = ((unsigned long long)(uint32_t)c.stamp[v] << 32) | (uint32_t)v;
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const int w = c.resd[j];
+            if (c.mark[w] == ep &&
+                (((unsigned long long)(uint32_t)c.stamp[w] << 32) | (uint32_t)w) < kv)
+                ++rank;
+        }
+        c.llits[base + rank] = vget(c.valb, v) == VT ? v : -v;
+    }
+    bar();
+    *nN_out = nN;
+    *bj_out = kk > 1 ? kk : 1;
+    return 1;
+}
+
+// Fwd-learning (Sect. 4.2, Alg. 4) -- or Res-learning (Alg. 3) -- +
+// Backjump + assertion.
 DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     const int T = c.T, tid = c.tid, W = c.W;
     c.scr->pool_top = k.pool_top;
@@ -867,6 +973,19 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     hi1 = uni(hi1);
     hi2 = uni(hi2);
     npop = uni(npop);
+    const bool res = c.learning == LEARN_RES && k.pend_kind == 1;
+    if (res) {
+        // Res-learning: a conflict with no literal above level 1 holds at the root
+        const int32_t* lits;
+        int len;
+        ng_span(c, k, k.pending, lits, len);
+        unsigned long long mx = 0ull;
+        for (int q = tid; q < len; q += T) {
+            const unsigned long long l = (unsigned long long)c.lvl[lvar(lits[q])];
+            mx = l > mx ? l : mx;
+        }
+        zero = block_max_u64(c, mx) <= 1ull;
+    }
     if (zero) {
         // the conflict follows from level-1 facts alone
         k.conflicts += 1;
@@ -890,58 +1009,69 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
             k.hash = fnv(k.hash, 7);
         }
     }
-    int topl, bj, nN;
-    if (sat) {
-        topl = k.cdl;
-        bj = (k.cdl - 1 >= 64 * W) ? k.cdl - 1 : (hi1 >= 0 ? hi1 + 1 : 1);
-        nN = npop + (k.cdl - 64 * W + 1);
-    } else {
-        topl = hi1 + 1;
-        bj = hi2 >= 0 ? hi2 + 1 : 1;
-        nN = npop;
-    }
-    if (hi1 + 1 > k.cdl || (sat && k.cdl < 64 * W) || topl < 2) {
-        // Deps named a level above cdl: broken invariant
-        k.status = ST_E_INTERNAL;
-        bar();
-        return;
-    }
-    if (k.n_learned + 1 > a.cap_ng || k.learned_lits + nN > a.cap_lits) {
-        k.status = ST_UNKNOWN;
-        bar();
-        return;
-    }
     const int base = uni(c.loff[k.n_learned]);
     const int cdl = k.cdl;
     const int newid = k.nS + k.n_learned;
+    int bj = 1, nN = 0, got = 0;
+    if (res) {
+        got = res_learn(c, k, a, base, &nN, &bj);
+        if (got < 0) {
+            k.status = ST_UNKNOWN;
+            bar();
+            return;
+        }
+    }
+    if (!got) {
+        // Fwd-learning: the decision literal of every level in levels(B),
+        // by increasing level
+        int topl;
+        if (sat) {
+            topl = k.cdl;
+            bj = (k.cdl - 1 >= 64 * W) ? k.cdl - 1 : (hi1 >= 0 ? hi1 + 1 : 1);
+            nN = npop + (k.cdl - 64 * W + 1);
+        } else {
+            topl = hi1 + 1;
+            bj = hi2 >= 0 ? hi2 + 1 : 1;
+            nN = npop;
+        }
+        if (hi1 + 1 > k.cdl || (sat && k.cdl < 64 * W) || topl < 2) {
+            // Deps named a level above cdl: broken invariant
+            k.status = ST_E_INTERNAL;
+            bar();
+            return;
+        }
+        if (k.n_learned + 1 > a.cap_ng || k.learned_lits + nN > a.cap_lits) {
+            k.status = ST_UNKNOWN;
+            bar();
+            return;
+        }
+        bar();
+        for (int w = tid; w < W; w += T) {
+            int pos = 0;
+            for (int w2 = 0; w2 < w; ++w2) {
+                unsigned long long y = c.sB[w2];
+                if (w2 == W - 1) y &= ~(1ull << 63);
+                if (w2 == 0) y &= ~1ull;
+                pos += __popcll(y);
+            }
+            unsigned long long x = c.sB[w];
+            if (w == W - 1) x &= ~(1ull << 63);
+            if (w == 0) x &= ~1ull;
+            while (x) {
+                int b = __ffsll((long long)x) - 1;
+                x &= x - 1ull;
+                c.llits[base + pos] = c.dec[w * 64 + b + 1];
+                ++pos;
+            }
+        }
+        if (sat)
+            for (int l = 64 * W + tid; l <= cdl; l += T) c.llits[base + npop + (l - 64 * W)] = c.dec[l];
+    }
     k.hash = fnv(k.hash, 2);
     k.hash = fnv(k.hash, k.pend_kind == 1 ? k.pending : -1);
     k.hash = fnv(k.hash, nN);
     k.hash = fnv(k.hash, bj);
-    bar();
     c.loff[k.n_learned + 1] = base + nN;
-    // the learned nogood: the decision literal of every level in levels(B),
-    // by increasing level
-    for (int w = tid; w < W; w += T) {
-        int pos = 0;
-        for (int w2 = 0; w2 < w; ++w2) {
-            unsigned long long y = c.sB[w2];
-            if (w2 == W - 1) y &= ~(1ull << 63);
-            if (w2 == 0) y &= ~1ull;
-            pos += __popcll(y);
-        }
-        unsigned long long x = c.sB[w];
-        if (w == W - 1) x &= ~(1ull << 63);
-        if (w == 0) x &= ~1ull;
-        while (x) {
-            int b = __ffsll((long long)x) - 1;
-            x &= x - 1ull;
-            c.llits[base + pos] = c.dec[w * 64 + b + 1];
-            ++pos;
-        }
-    }
-    if (sat)
-        for (int l = 64 * W + tid; l <= cdl; l += T) c.llits[base + npop + (l - 64 * W)] = c.dec[l];
     bar();
     // literal occurrence lists of the new nogood (one lane per literal; the
     // literals are distinct): doubling arrays in the slot's pool
@@ -994,6 +1124,8 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     for (int w = tid; w < W; w += T) c.deps[(size_t)x * W + w] = c.sB[w];
     vset(c.valb, x, top > 0 ? VF : VT);   // identical from every lane
     c.lvl[x] = bj;
+    c.stamp[x] = k.clock;
+    c.reason[x] = newid;
     c.trail[start] = x;
     bar();
     for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
@@ -1003,6 +1135,7 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     k.qh = start;
     k.qt = start + 1;
     k.fr_ok = 1;
+    k.clock += 1;
     k.pending = -1;
     k.pend_kind = 0;
     k.n_learned += 1;
@@ -1061,6 +1194,8 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         c.tlim[ncdl] = k.qt;                 // identical stores from every lane
         c.dec[ncdl] = b;
         c.lvl[b] = ncdl;
+        c.stamp[b] = k.clock;
+        c.reason[b] = -1;
         c.trail[k.qt] = b;
         vset(c.valb, b, VT);
         put_record(c, 0, b, VT, bit < 64 ? (1ull << bit) : 0ull);   // identical from every lane
@@ -1069,6 +1204,7 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         k.qh = k.qt;
         k.qt = k.qt + 1;
         k.fr_ok = 1;
+        k.clock += 1;
         k.decisions += 1;
         k.dec_open = 1;
         k.hash = fnv(k.hash, 1);
@@ -1083,6 +1219,8 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         if (vget(c.valb, p) != 0u) continue;
         for (int w = 0; w < W; ++w) c.deps[(size_t)p * W + w] = alldec_word(w, cdl, W);
         c.lvl[p] = cdl;
+        c.stamp[p] = k.clock;
+        c.reason[p] = -1;
         int pos = atomicAdd(&c.scr->tail, 1);
         c.trail[pos] = p;
     }
@@ -1097,6 +1235,7 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
     k.qh = k.qt;
     k.qt = nt;
     k.fr_ok = 0;
+    k.clock += 1;
     if (n == 0) k.status = ST_E_INTERNAL;
     return STEP_COMPLETE;
 }
@@ -1272,6 +1411,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void 
     c.W = a.W;
     c.decision = a.decision;
     c.fallback_after = a.fallback_after;
+    c.learning = a.learning;
     c.T = MAXT;
     c.tid = threadIdx.x;
     c.lane = threadIdx.x & 63;

@@ -54,7 +54,7 @@ struct SlotCtrl {
     int32_t n_learned, pool_top, pending, pend_kind;  // pend_kind 0 none, 1 round, 2 gate
     int32_t status, init_done, last_step, use_score;
     int32_t consec, dec_open;                // learned-Decision fallback state
-    int32_t clock, epoch;                    // assignment clock, resolution marks
+    int32_t epoch, pad_e;                    // resolution marks
     int64_t learned_lits;
     int64_t rounds, visits, checks, props, decisions, conflicts, learned, learned_len,
             gate_fail, completes;
@@ -78,7 +78,7 @@ struct SlotLayout {
     int64_t l_off;      // int32[cap_ng+1]
     int64_t l_lits;     // int32[cap_lits]
     int64_t pool;       // int32[pool_cap]
-    int64_t stamp;      // int32[V+1] assignment clock tick (Res-learning order)
+    int64_t gpos;       // int32[V+1] trail position where the assigning step begins
     int64_t reason;     // int32[V+1] nogood that implied the assignment, -1 none
     int64_t mark;       // int32[V+1] resolution membership (epoch)
     int64_t resd;       // int32[V+1] variables of the nogood being resolved
@@ -113,7 +113,7 @@ __host__ __device__ inline SlotLayout slot_layout(int64_t V, int64_t Rh, int32_t
     const int64_t lists = learning ? (cap_lits < 2 * V1 ? cap_lits : 2 * V1) : Rh + 1;
     L.pool_cap = 4 * cap_lits + 8 * lists;
     ASP_TAKE(pool, 4 * L.pool_cap);
-    ASP_TAKE(stamp, 4 * V1);
+    ASP_TAKE(gpos, 4 * V1);
     ASP_TAKE(reason, 4 * V1);
     ASP_TAKE(mark, 4 * V1);
     ASP_TAKE(resd, 4 * V1);

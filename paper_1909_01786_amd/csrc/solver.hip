@@ -61,7 +61,7 @@ struct Ctl {
     int32_t cdl, qh, qt, n_learned, pend_kind, pending, status, init_done, last_step, pool_top;
     int32_t use_score, consec, dec_open;   // score-driven Decision and its fallback
     int32_t fr_ok;    // the LDS records describe the frontier trail[qh..qt)
-    int32_t clock, epoch;   // assignment clock and resolution-mark epoch (Res-learning)
+    int32_t epoch;          // resolution-mark epoch (Res-learning)
     int64_t learned_lits, rounds, props, decisions, conflicts, learned, learned_len, gate_fail,
             completes, steps, visits, checks;
     uint64_t hash;
@@ -87,7 +87,7 @@ struct Ctx {
     SlotCtrl* ctrl;
     int8_t* val8;
     int32_t *lvl, *trail, *tlim, *dec, *lptr, *ln, *lcap, *loff, *llits, *pool;
-    int32_t *stamp, *reason, *mark, *resd;
+    int32_t *gpos, *reason, *mark, *resd;
     unsigned long long* win;
     uint64_t* deps;
     int64_t pool_cap;
@@ -162,7 +162,7 @@ DEV int wave_incl_scan(int x, int lane) {
     return x;
 }
 
-// Exclusive scan over the block; every lane must call it.
+// Block-wide reductions; every lane must call them.
 DEV unsigned long long block_max_u64(Ctx& c, unsigned long long x) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
@@ -203,6 +203,28 @@ DEV int block_min_i32(Ctx& c, int x) {
         r = r < v ? r : v;
     }
     return uni(r);
+}
+
+// Sum of `cnt` and minimum of `mn` over the block, with one pair of barriers.
+DEV void block_sum_min(Ctx& c, int cnt, int mn, int* sum_out, int* min_out) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        cnt += __shfl_xor(cnt, d, 64);
+        const int y = __shfl_xor(mn, d, 64);
+        mn = mn < y ? mn : y;
+    }
+    bar();
+    c.scr->red[c.wid] = ((unsigned long long)(uint32_t)cnt << 32) | (uint32_t)mn;
+    bar();
+    int sm = 0, m = 0x7fffffff;
+    for (int i = 0; i < c.nw; ++i) {
+        const unsigned long long r = c.scr->red[i];
+        sm += (int)(r >> 32);
+        const int v = (int)(uint32_t)r;
+        m = m < v ? m : v;
+    }
+    *sum_out = uni(sm);
+    *min_out = uni(m);
 }
 
 // OR of a per-wave flag over the block.
@@ -319,7 +341,7 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     c.loff = (int32_t*)(slot + lay.l_off);
     c.llits = (int32_t*)(slot + lay.l_lits);
     c.pool = (int32_t*)(slot + lay.pool);
-    c.stamp = (int32_t*)(slot + lay.stamp);
+    c.gpos = (int32_t*)(slot + lay.gpos);
     c.reason = (int32_t*)(slot + lay.reason);
     c.mark = (int32_t*)(slot + lay.mark);
     c.resd = (int32_t*)(slot + lay.resd);
@@ -368,7 +390,7 @@ DEV void reset_search(Ctx& c, Ctl& k) {
     k.dec_open = 0;
     k.t_round = k.t_learn = k.t_decide = k.t_gate = 0;
     k.fr_ok = 0;
-    k.clock = k.epoch = 0;
+    k.epoch = 0;
     tab_clear_all(c);
     bar();
 }
@@ -415,7 +437,6 @@ DEV void load_ctrl(Ctx& c, Ctl& k) {
     k.use_score = uni(g.use_score);
     k.consec = uni(g.consec);
     k.dec_open = uni(g.dec_open);
-    k.clock = uni(g.clock);
     k.epoch = uni(g.epoch);
     k.steps = 0;
     k.t_round = k.t_learn = k.t_decide = k.t_gate = 0;
@@ -467,7 +488,6 @@ DEV void save_ctrl(Ctx& c, const Ctl& k) {
     g.use_score = k.use_score;
     g.consec = k.consec;
     g.dec_open = k.dec_open;
-    g.clock = k.clock;
     g.epoch = k.epoch;
     bar();
 }
@@ -506,8 +526,10 @@ DEV void step_init(Ctx& c, Ctl& k) {
             uint32_t code = vget(c.pendb, x);
             vset(c.valb, x, code);
             c.lvl[x] = 1;
-            c.stamp[x] = k.clock;
-            c.reason[x] = -1;    // never resolved: conflicts at level 1 mean UNSAT
+            if (c.learning == LEARN_RES) {
+                c.gpos[x] = q0;
+                c.reason[x] = -1;    // never resolved: conflicts at level 1 mean UNSAT
+            }
         }
     }
     bar();
@@ -519,7 +541,6 @@ DEV void step_init(Ctx& c, Ctl& k) {
     } else {
         k.qh = q0;
         k.qt = q1;
-        k.clock += 1;
     }
     k.fr_ok = 0;
 }
@@ -574,14 +595,24 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
             c.my_visits += 1ull;
             c.my_checks += (unsigned long long)len;
         }
-        for (int q = 0; q < len; ++q) {
-            const int l = lits[q];
-            const uint32_t s = vget(c.valb, lvar(l));
-            if (s == 0u) {
-                if (++open > 1) return;
-                u = l;
-            } else if (s != lcode(l)) {
-                return;  // satisfied
+        // from the last literal back, four loads in flight: a learned
+        // nogood holds its newest literal last, the one most likely to be
+        // open or false after a backjump (the outcome -- violated, unit on
+        // one literal, or neither -- does not depend on the order)
+        for (int q = len; q > 0; q -= 4) {
+            int l[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) l[j] = j < q ? lits[q - 1 - j] : 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j >= q) break;
+                const uint32_t s = vget(c.valb, lvar(l[j]));
+                if (s == 0u) {
+                    if (++open > 1) return;
+                    u = l[j];
+                } else if (s != lcode(l[j])) {
+                    return;  // satisfied
+                }
             }
         }
     }
@@ -813,8 +844,10 @@ DEV void step_round(Ctx& c, Ctl& k) {
             if (rec) put_record(c, i - qt, x, code, dx[0]);
         }
         c.lvl[x] = cdl;
-        c.stamp[x] = k.clock;
-        c.reason[x] = id;
+        if (c.learning == LEARN_RES) {
+            c.gpos[x] = qt;
+            c.reason[x] = id;
+        }
         vset(c.valb, x, code);
         vclr(c.pendb, x);
     }
@@ -836,7 +869,6 @@ DEV void step_round(Ctx& c, Ctl& k) {
     k.qh = qt;
     k.qt = nt;
     k.fr_ok = rec ? 1 : 0;
-    k.clock += 1;
     k.rounds += 1;
     k.props += nt - qt;
     if (ck != ~0ull) {
@@ -845,83 +877,162 @@ DEV void step_round(Ctx& c, Ctl& k) {
     }
 }
 
-// Res-learning (Alg. 3) of the pending round conflict: while the literal
-// assigned last (clock tick, then variable) shares its level with another
-// literal, resolve it away with the nogood that implied it.  Writes the
-// first-UIP nogood's true literals by assignment order (the UIP last) to
-// the learned store at `base`.  Returns 1, or 0 when the literal to resolve
-// has no implying nogood (a CompleteAssignment literal; the caller learns
-// by Fwd-learning), or -1 when the learned store is full.
-DEV int res_learn(Ctx& c, Ctl& k, const KArgs& a, int base, int* nN_out, int* bj_out) {
+// Res-learning (Alg. 3) of the pending round conflict at level `top`,
+// resolution to the first UIP.  The trail is walked back one assigning step
+// at a time (a round, a decision, an assertion, a CompleteAssignment; gpos
+// gives the trail position where a variable's step begins, so (gpos,
+// variable) orders the assigned variables as they were assigned, and an
+// implying nogood's other variables come from earlier steps).  The marked
+// variables of one step all sit at the top level: every one but the lowest
+// numbered is resolved away with the nogood that implied it (none of them
+// can be the last marked variable at the top level), and the lowest
+// numbered is the UIP when it is the only marked variable left there, else
+// it is resolved too.  Writes the nogood's literals (true now) ordered by
+// (gpos, variable), the UIP last, to the learned store at `base`.  Returns
+// 1; 0 when a variable to resolve has no implying nogood (a
+// CompleteAssignment literal: the caller learns by Fwd-learning); -1 when
+// the learned store is full; -2 on a broken invariant.
+DEV int res_learn(Ctx& c, Ctl& k, const KArgs& a, int base, int top, int* nN_out, int* bj_out) {
     const int T = c.T, tid = c.tid;
     const int ep = k.epoch + 1;
     k.epoch = ep;
     const int32_t* lits;
     int len;
     ng_span(c, k, k.pending, lits, len);
+    c.scr->tail = len;                         // identical from every lane
+    unsigned long long at_top = 0ull;
     for (int q = tid; q < len; q += T) {
         const int v = lvar(lits[q]);
         c.mark[v] = ep;
         c.resd[q] = v;
+        at_top += c.lvl[v] == top ? 1ull : 0ull;
     }
-    int n = len, kk = 0;
-    bar();
-    for (;;) {
-        unsigned long long best = 0ull;
-        for (int i = tid; i < n; i += T) {
-            const int v = c.resd[i];
+    int ntop = (int)block_sum_u64(c, at_top);  // (its barriers order the marks)
+    int p = k.qt - 1, uip = -1;
+    while (uip < 0) {
+        if (p < 0) return -2;
+        // the latest marked variable at or below p, T trail positions at a time
+        {
+            const int i = p - tid;
+            const int hm = (int)block_max_u64(
+                c, (i >= 0 && c.mark[c.trail[i]] == ep) ? (unsigned long long)(i + 1) : 0ull);
+            if (hm == 0) {
+                p -= T;
+                continue;
+            }
+            p = hm - 1;
+        }
+        const int g0 = uni(c.gpos[uni(c.trail[p])]);
+        // the marked variables of the step trail[g0..p]: how many, the lowest
+        int cnt = 0, mn = 0x7fffffff;
+        for (int i = g0 + tid; i <= p; i += T) {
+            const int v = c.trail[i];
             if (c.mark[v] == ep) {
-                const unsigned long long key = ((unsigned long long)(uint32_t)c.stamp[v] << 32) | (uint32_t)v;
-                best = key > best ? key : best;
+                cnt += 1;
+                mn = v < mn ? v : mn;
             }
         }
-        const int sig = (int)(uint32_t)(block_max_u64(c, best) & 0xffffffffull);
-        unsigned long long mk = 0ull;
-        for (int i = tid; i < n; i += T) {
-            const int v = c.resd[i];
-            if (c.mark[v] == ep && v != sig) {
-                const unsigned long long l = (unsigned long long)c.lvl[v];
-                mk = l > mk ? l : mk;
+        int m;
+        block_sum_min(c, cnt, mn, &m, &mn);
+        c.scr->clash = 0;                      // set: a variable without implying nogood
+        c.scr->nimpl = 0;                      // newly marked variables at the top level
+        bar();
+        if (m > 1) {
+            for (int i = g0 + tid; i <= p; i += T) {
+                const int v = c.trail[i];
+                if (v == mn || c.mark[v] != ep) continue;
+                const int e = c.reason[v];
+                if (e < 0) {
+                    c.scr->clash = 1;
+                    continue;
+                }
+                c.mark[v] = 0;
+                const int32_t* E;
+                int elen;
+                ng_span(c, k, e, E, elen);
+                for (int q = 0; q < elen; ++q) {
+                    const int w = lvar(E[q]);
+                    if (w == v || atomicExch(&c.mark[w], ep) == ep) continue;
+                    c.resd[atomicAdd(&c.scr->tail, 1)] = w;
+                    if (c.lvl[w] == top) atomicAdd(&c.scr->nimpl, 1);
+                }
             }
+            bar();
+            if (uni(c.scr->clash)) return 0;
+            ntop += uni(c.scr->nimpl) - (m - 1);
         }
-        kk = (int)block_max_u64(c, mk);
-        if (uni(c.lvl[sig]) != kk) break;
-        const int e = uni(c.reason[sig]);
+        if (ntop == 1) {
+            uip = mn;
+            break;
+        }
+        // the lowest numbered is resolved too, the block over its nogood
+        const int e = uni(c.reason[mn]);
         if (e < 0) return 0;
-        // resolve sigma away with its reason: add the reason's other variables
-        c.scr->tail = 0;
-        c.mark[sig] = 0;                       // identical from every lane
+        bar();
+        c.scr->nimpl = 0;
+        c.mark[mn] = 0;                        // identical from every lane
         bar();
         const int32_t* E;
         int elen;
         ng_span(c, k, e, E, elen);
         for (int q = tid; q < elen; q += T) {
-            const int v = lvar(E[q]);
-            if (v != sig && c.mark[v] != ep) {
-                c.mark[v] = ep;
-                c.resd[n + atomicAdd(&c.scr->tail, 1)] = v;
-            }
+            const int w = lvar(E[q]);
+            if (w == mn || atomicExch(&c.mark[w], ep) == ep) continue;
+            c.resd[atomicAdd(&c.scr->tail, 1)] = w;
+            if (c.lvl[w] == top) atomicAdd(&c.scr->nimpl, 1);
         }
         bar();
-        n += uni(c.scr->tail);
+        ntop += uni(c.scr->nimpl) - 1;
+        if (ntop < 1) return -2;
+        p = g0 - 1;
     }
-    // the live variables in assignment order
-    unsigned long long m = 0ull;
-    for (int i = tid; i < n; i += T) m += c.mark[c.resd[i]] == ep ? 1ull : 0ull;
-    const int nN = (int)block_sum_u64(c, m);
-    if (k.n_learned + 1 > a.cap_ng || k.learned_lits + nN > a.cap_lits) return -1;
-    for (int i = tid; i < n; i += T) {
-        const int v = c.resd[i];
-        if (c.mark[v] != ep) continue;
-        const unsigned long long kv = ((unsigned long long)(uint32_t)c.stamp[v] << 32) | (uint32_t)v;
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const int w = c.resd[j];
-            if (c.mark[w] == ep &&
-                (((unsigned long long)(uint32_t)c.stamp[w] << 32) | (uint32_t)w) < kv)
-                ++rank;
+    // the live (still marked) variables, compacted in place chunk by chunk
+    // (a chunk is read before any of it is overwritten; writes stay below
+    // the next chunk), and the highest level among them but the UIP's
+    const int n = uni(c.scr->tail);
+    bar();
+    c.scr->nimpl = 0;
+    bar();
+    unsigned long long mk = 0ull;
+    for (int b = 0; b < n; b += T) {
+        const int i = b + tid;
+        const int v = i < n ? c.resd[i] : 0;
+        const bool live = i < n && c.mark[v] == ep;
+        bar();
+        if (live) {
+            c.resd[atomicAdd(&c.scr->nimpl, 1)] = v;
+            if (v != uip) {
+                const unsigned long long l = (unsigned long long)c.lvl[v];
+                mk = l > mk ? l : mk;
+            }
         }
-        c.llits[base + rank] = vget(c.valb, v) == VT ? v : -v;
+    }
+    const int kk = (int)block_max_u64(c, mk);
+    const int nN = uni(c.scr->nimpl);
+    if (k.n_learned + 1 > a.cap_ng || k.learned_lits + nN > a.cap_lits) return -1;
+    // each live variable's rank by (gpos, variable), counted against tiles
+    // of the keys staged in LDS
+    unsigned long long* tile = c.sDeps;
+    for (int r = 0; r < nN; r += T) {
+        const int i = r + tid;
+        const int v = i < nN ? c.resd[i] : 0;
+        const unsigned long long kv =
+            i < nN ? (((unsigned long long)(uint32_t)c.gpos[v] << 32) | (uint32_t)v) : ~0ull;
+        int rank = 0;
+        for (int t0 = 0; t0 < nN; t0 += T) {
+            bar();
+            const int j = t0 + tid;
+            if (j < nN) {
+                const int w = c.resd[j];
+                tile[tid] = ((unsigned long long)(uint32_t)c.gpos[w] << 32) | (uint32_t)w;
+            } else {
+                tile[tid] = ~0ull;
+            }
+            bar();
+            const int nt = nN - t0 < T ? nN - t0 : T;
+            for (int jj = 0; jj < nt; ++jj) rank += tile[jj] < kv ? 1 : 0;
+        }
+        if (i < nN) c.llits[base + rank] = vget(c.valb, v) == VT ? v : -v;
     }
     bar();
     *nN_out = nN;
@@ -974,6 +1085,7 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     hi2 = uni(hi2);
     npop = uni(npop);
     const bool res = c.learning == LEARN_RES && k.pend_kind == 1;
+    int ctop = 0;
     if (res) {
         // Res-learning: a conflict with no literal above level 1 holds at the root
         const int32_t* lits;
@@ -984,7 +1096,8 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
             const unsigned long long l = (unsigned long long)c.lvl[lvar(lits[q])];
             mx = l > mx ? l : mx;
         }
-        zero = block_max_u64(c, mx) <= 1ull;
+        ctop = (int)block_max_u64(c, mx);
+        zero = ctop <= 1;
     }
     if (zero) {
         // the conflict follows from level-1 facts alone
@@ -1014,9 +1127,9 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     const int newid = k.nS + k.n_learned;
     int bj = 1, nN = 0, got = 0;
     if (res) {
-        got = res_learn(c, k, a, base, &nN, &bj);
+        got = res_learn(c, k, a, base, ctop, &nN, &bj);
         if (got < 0) {
-            k.status = ST_UNKNOWN;
+            k.status = got == -1 ? ST_UNKNOWN : ST_E_INTERNAL;
             bar();
             return;
         }
@@ -1124,8 +1237,10 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     for (int w = tid; w < W; w += T) c.deps[(size_t)x * W + w] = c.sB[w];
     vset(c.valb, x, top > 0 ? VF : VT);   // identical from every lane
     c.lvl[x] = bj;
-    c.stamp[x] = k.clock;
-    c.reason[x] = newid;
+    if (c.learning == LEARN_RES) {
+        c.gpos[x] = start;
+        c.reason[x] = newid;
+    }
     c.trail[start] = x;
     bar();
     for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
@@ -1135,7 +1250,6 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     k.qh = start;
     k.qt = start + 1;
     k.fr_ok = 1;
-    k.clock += 1;
     k.pending = -1;
     k.pend_kind = 0;
     k.n_learned += 1;
@@ -1194,8 +1308,10 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         c.tlim[ncdl] = k.qt;                 // identical stores from every lane
         c.dec[ncdl] = b;
         c.lvl[b] = ncdl;
-        c.stamp[b] = k.clock;
-        c.reason[b] = -1;
+        if (c.learning == LEARN_RES) {
+            c.gpos[b] = k.qt;
+            c.reason[b] = -1;
+        }
         c.trail[k.qt] = b;
         vset(c.valb, b, VT);
         put_record(c, 0, b, VT, bit < 64 ? (1ull << bit) : 0ull);   // identical from every lane
@@ -1204,7 +1320,6 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         k.qh = k.qt;
         k.qt = k.qt + 1;
         k.fr_ok = 1;
-        k.clock += 1;
         k.decisions += 1;
         k.dec_open = 1;
         k.hash = fnv(k.hash, 1);
@@ -1219,8 +1334,10 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
         if (vget(c.valb, p) != 0u) continue;
         for (int w = 0; w < W; ++w) c.deps[(size_t)p * W + w] = alldec_word(w, cdl, W);
         c.lvl[p] = cdl;
-        c.stamp[p] = k.clock;
-        c.reason[p] = -1;
+        if (c.learning == LEARN_RES) {
+            c.gpos[p] = k.qt;
+            c.reason[p] = -1;
+        }
         int pos = atomicAdd(&c.scr->tail, 1);
         c.trail[pos] = p;
     }
@@ -1235,7 +1352,6 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
     k.qh = k.qt;
     k.qt = nt;
     k.fr_ok = 0;
-    k.clock += 1;
     if (n == 0) k.status = ST_E_INTERNAL;
     return STEP_COMPLETE;
 }
@@ -1401,8 +1517,10 @@ DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a, uint64_t t0) {
 }
 
 // Three waves per SIMD: the register budget (168 VGPRs) at which the
-// search keeps six 128-thread workgroups resident per CU.
-template <int MAXT>
+// search keeps six 128-thread workgroups resident per CU.  The Learning
+// step is a compile-time parameter: the Fwd-learning kernel carries none
+// of Res-learning's code or registers.
+template <int MAXT, int LR>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void k_search(KArgs a) {
     HIP_DYNAMIC_SHARED(unsigned long long, smem64);  // 8-byte aligned base
     __shared__ Scr scr;
@@ -1411,7 +1529,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void 
     c.W = a.W;
     c.decision = a.decision;
     c.fallback_after = a.fallback_after;
-    c.learning = a.learning;
+    c.learning = LR;
     c.T = MAXT;
     c.tid = threadIdx.x;
     c.lane = threadIdx.x & 63;
@@ -1478,37 +1596,59 @@ size_t lds_bytes(int threads, int words) {
            sizeof(unsigned long long) * ((size_t)kFrontCap + (size_t)threads);
 }
 
-hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {
+template <int LR>
+static const void* search_fn_lr(int threads) {
     switch (threads) {
-    case 64: hipLaunchKernelGGL(k_search<64>, dim3(grid), dim3(64), lds, s, a); break;
-    case 128: hipLaunchKernelGGL(k_search<128>, dim3(grid), dim3(128), lds, s, a); break;
-    case 256: hipLaunchKernelGGL(k_search<256>, dim3(grid), dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL(k_search<512>, dim3(grid), dim3(512), lds, s, a); break;
-    case 1024: hipLaunchKernelGGL(k_search<1024>, dim3(grid), dim3(1024), lds, s, a); break;
+    case 64: return (const void*)k_search<64, LR>;
+    case 128: return (const void*)k_search<128, LR>;
+    case 256: return (const void*)k_search<256, LR>;
+    case 512: return (const void*)k_search<512, LR>;
+    case 1024: return (const void*)k_search<1024, LR>;
+    default: return nullptr;
+    }
+}
+
+static const void* search_fn(int threads, int learning) {
+    switch (learning) {
+    case LEARN_FWD: return search_fn_lr<LEARN_FWD>(threads);
+    case LEARN_RES: return search_fn_lr<LEARN_RES>(threads);
+    default: return nullptr;
+    }
+}
+
+template <int LR>
+static hipError_t launch_lr(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {
+    switch (threads) {
+    case 64: hipLaunchKernelGGL((k_search<64, LR>), dim3(grid), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((k_search<128, LR>), dim3(grid), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_search<256, LR>), dim3(grid), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_search<512, LR>), dim3(grid), dim3(512), lds, s, a); break;
+    case 1024: hipLaunchKernelGGL((k_search<1024, LR>), dim3(grid), dim3(1024), lds, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-static const void* search_fn(int threads) {
-    switch (threads) {
-    case 64: return (const void*)k_search<64>;
-    case 128: return (const void*)k_search<128>;
-    case 256: return (const void*)k_search<256>;
-    case 512: return (const void*)k_search<512>;
-    case 1024: return (const void*)k_search<1024>;
-    default: return nullptr;
+hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {
+    switch (a.learning) {
+    case LEARN_FWD: return launch_lr<LEARN_FWD>(a, threads, grid, lds, s);
+    case LEARN_RES: return launch_lr<LEARN_RES>(a, threads, grid, lds, s);
+    default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t set_max_lds(int threads, size_t lds) {
-    const void* f = search_fn(threads);
-    if (!f) return hipErrorInvalidValue;
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    for (int lr : {(int)LEARN_FWD, (int)LEARN_RES}) {
+        const void* f = search_fn(threads, lr);
+        if (!f) return hipErrorInvalidValue;
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t occupancy(int threads, size_t lds, int* blocks_per_cu) {
-    const void* f = search_fn(threads);
+hipError_t occupancy(int threads, int learning, size_t lds, int* blocks_per_cu) {
+    const void* f = search_fn(threads, learning);
     if (!f) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, lds);
 }

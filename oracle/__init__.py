@@ -34,7 +34,8 @@ STEP_NAMES = {ST_INIT: "init", ST_ROUND: "round", ST_LEARN: "learn", ST_DECIDE: 
 class Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "rounds", "visits", "literal_checks", "propagations", "decisions", "conflicts",
-        "learned", "learned_len", "gate_failures", "completes")] + [("trace_hash", C.c_uint64)]
+        "learned", "learned_len", "gate_failures", "completes", "models", "restarts")] + \
+        [("trace_hash", C.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -94,7 +95,12 @@ def lib():
         L.or_model.argtypes = [P, np.ctypeslib.ndpointer(np.uint8, flags="C")]
         L.or_solve.argtypes = [C.c_int32, C.c_int32, i32p, i64p, i32p, C.c_int32, C.c_int32,
                                C.POINTER(Limits), np.ctypeslib.ndpointer(np.uint8, flags="C"),
-                               C.POINTER(Stats), C.c_void_p, C.c_int32, C.c_int32]
+                               C.POINTER(Stats), C.c_void_p, C.c_int32, C.c_int32, C.c_int64,
+                               C.c_int64]
+        L.or_set_enum.argtypes = [P, C.c_int64, C.c_int64]
+        L.or_set_enum.restype = C.c_int32
+        L.or_models.argtypes = [P, np.ctypeslib.ndpointer(np.uint8, flags="C"), C.c_int64]
+        L.or_models.restype = C.c_int64
         L.or_set_learning.argtypes = [P, C.c_int32]
         L.or_set_learning.restype = C.c_int32
         L.or_set_scores.argtypes = [P, i32p, C.c_int32]
@@ -134,7 +140,8 @@ class State:
 class Solver:
     """One program in the oracle, steppable."""
 
-    def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED, learning: int = LEARN_FWD):
+    def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED, learning: int = LEARN_FWD,
+                 max_models: int = 1, restart_every: int = 0):
         L = lib()
         err = C.c_int32(0)
         self._h = L.or_create(int(prog.n_atoms), int(prog.n_rules),
@@ -147,6 +154,8 @@ class Solver:
         self.W = W
         if L.or_set_learning(self._h, int(learning)) != 0:
             raise ValueError("unknown learning mode")
+        if L.or_set_enum(self._h, int(max_models), int(restart_every)) != 0:
+            raise ValueError("max_models and restart_every must be >= 0")
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -193,6 +202,18 @@ class Solver:
         lib().or_model(self._h, m)
         return m[:A]
 
+    def models(self) -> list:
+        """The answer sets found so far, in the order found."""
+        A = int(self.dims()[1])
+        n = int(self.stats()["models"])
+        buf = np.zeros(max(n * A, 1), np.uint8)
+        lib().or_models(self._h, buf, n)
+        return [buf[k * A:(k + 1) * A].copy() for k in range(n)]
+
+    def exhausted(self) -> bool:
+        """True once the search has shown that no further answer set exists."""
+        return bool(self.dims()[15])
+
     def nogoods(self):
         d = self.dims()
         n = int(d[3] + d[8])
@@ -224,9 +245,11 @@ class Solver:
 
 
 def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = None,
-          scores=None, fallback_after: int = 10, learning: int = LEARN_FWD):
+          scores=None, fallback_after: int = 10, learning: int = LEARN_FWD,
+          max_models: int = 1, restart_every: int = 0):
     """Encode and solve in one call; returns (status, model or None, stats).
-    ``scores`` (int32[n_atoms + 1]) selects the score-driven Decision."""
+    ``scores`` (int32[n_atoms + 1]) selects the score-driven Decision; the
+    model is the first answer set found."""
     L = lib()
     A = int(prog.n_atoms)
     m = np.zeros(max(A, 1), np.uint8)
@@ -241,5 +264,16 @@ def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = 
                     np.ascontiguousarray(prog.body_lits, np.int32), int(W), int(gate),
                     C.byref(limits) if limits else None, m, C.byref(st),
                     sc.ctypes.data if sc is not None else None, int(fallback_after),
-                    int(learning))
+                    int(learning), int(max_models), int(restart_every))
     return rc, (m[:A].copy() if rc == SAT else None), st.as_dict()
+
+
+def enumerate_models(prog, max_models: int = 0, restart_every: int = 0, W: int = 1,
+                     gate: int = GATE_UNFOUNDED, learning: int = LEARN_FWD,
+                     limits: Limits | None = None):
+    """Run the search for up to ``max_models`` answer sets (0: all); returns
+    (status, list of answer sets in the order found, stats, exhausted)."""
+    s = Solver(prog, W=W, gate=gate, learning=learning, max_models=max_models,
+               restart_every=restart_every)
+    rc = s.run(limits)
+    return rc, s.models(), s.stats(), s.exhausted()

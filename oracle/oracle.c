@@ -34,6 +34,22 @@
  *               (the answer-set definition of the Preliminaries); a failure
  *               becomes a conflict over the unfounded set's loop nogood.
  *
+ * Several answer sets and restarts (the paper restarts the solver when more
+ * than one answer set is asked for, or by a restart strategy, and its
+ * InitialPropagation then also takes the learned unit nogoods):
+ *   - an answer set M found while more are asked for is recorded and blocked
+ *     by the learned nogood {T p : p in M}: answer sets are pairwise
+ *     incomparable under set inclusion, so this excludes M and no other
+ *     answer set (an empty M leaves none); then the search restarts;
+ *   - a restart unassigns every variable, keeps every learned nogood, and
+ *     runs InitialPropagation again over the static and the learned unit
+ *     nogoods (an empty learned nogood means no answer set is left);
+ *   - with restart_every > 0, a conflict that makes restart_every conflicts
+ *     since the last restart learns its nogood and restarts in place of the
+ *     backjump;
+ *   - when the search ends UNSAT (or UNKNOWN) after at least one answer set,
+ *     the verdict is SAT; after UNSAT the enumeration is exhausted.
+ *
  * Readings of the paper taken here:
  *   - levels start at 1 (root); the decision at level l >= 2 sets Deps bit
  *     min(l-1, 64W-1), so bit 64W-1 stands for every level >= 64W;
@@ -70,7 +86,7 @@ enum { LEARN_FWD = 0, LEARN_RES = 1 };
 
 typedef struct {
     int64_t rounds, visits, literal_checks, propagations, decisions, conflicts,
-            learned, learned_len, gate_failures, completes;
+            learned, learned_len, gate_failures, completes, models, restarts;
     uint64_t trace_hash;
 } or_stats;
 
@@ -115,6 +131,13 @@ typedef struct {
     int32_t *reason;           /* [V+1] nogood that implied it, -1 if none */
     int32_t *mark;             /* [V+1] resolution membership (epoch) */
     int32_t epoch;
+    int64_t max_models;        /* answer sets asked for; 0: all */
+    int64_t restart_every;     /* conflicts between restarts; 0: never */
+    int64_t since_restart;     /* conflicts since the last restart */
+    int32_t need_init;         /* InitialPropagation comes next */
+    int32_t exhausted;         /* no answer set is left */
+    uint8_t *models;           /* [models found * A] answer sets found */
+    int64_t models_cap;
 
     /* assignment */
     int8_t *val;
@@ -370,6 +393,8 @@ void *or_create(int32_t n_atoms, int32_t n_rules, const int32_t *head,
     for (size_t v = 0; v < V1; ++v) s->reason[v] = -1;
     s->mark = (int32_t *)calloc(V1, sizeof(int32_t));
     s->cdl = 1;
+    s->max_models = 1;
+    s->need_init = 1;
     s->st.trace_hash = 1469598103934665603ull;
     s->status = OR_RUNNING;
     s->last_step = ST_NONE;
@@ -388,7 +413,7 @@ void or_free(void *h) {
     free(s->val); free(s->lvl); free(s->deps); free(s->tmpdeps); free(s->pend_B);
     free(s->dec); free(s->frontier.a); free(s->win); free(s->winsign); free(s->touched);
     free(s->inM); free(s->inLM);
-    free(s->stamp); free(s->reason); free(s->mark);
+    free(s->stamp); free(s->reason); free(s->mark); free(s->models);
     free(s);
 }
 
@@ -398,26 +423,35 @@ static int cmp_i32(const void *a, const void *b) {
     return (x > y) - (x < y);
 }
 
-/* S3: every unit nogood {l}, in id order, assigns the complement of l at
- * level 1 with empty Deps; two opposite units mean no answer set. */
+/* S3: every unit nogood {l} -- the static ones, then (after a restart) the
+ * learned ones, in id order -- assigns the complement of l at level 1 with
+ * empty Deps; two opposite units, or an empty nogood, mean no answer set. */
+static int init_unit(or_solver *s, int64_t id) {
+    int32_t l = ng_ptr(s, id)[0], x = var_of(l);
+    int8_t want = (int8_t)-lit_sign(l);
+    if (s->val[x] == 0) {
+        s->val[x] = want;
+        s->lvl[x] = 1;
+        s->stamp[x] = s->clock;
+        s->reason[x] = (int32_t)id;
+        s->nass += 1;
+        iv_push(&s->frontier, x);
+    } else if (s->val[x] != want) {
+        return 0;
+    }
+    return 1;
+}
+
 static void step_init(or_solver *s) {
+    s->need_init = 0;
     if (s->has_empty_nogood) { s->status = OR_UNSAT; return; }
     s->frontier.n = 0;
-    for (int64_t id = 0; id < s->n0 && ng_len(s, id) <= 1; ++id) {
-        if (ng_len(s, id) != 1) continue;
-        int32_t l = ng_ptr(s, id)[0], x = var_of(l);
-        int8_t want = (int8_t)-lit_sign(l);
-        if (s->val[x] == 0) {
-            s->val[x] = want;
-            s->lvl[x] = 1;
-            s->stamp[x] = s->clock;
-            s->reason[x] = (int32_t)id;
-            s->nass += 1;
-            iv_push(&s->frontier, x);
-        } else if (s->val[x] != want) {
-            s->status = OR_UNSAT;
-            return;
-        }
+    /* static nogoods are sorted by length: the units come first */
+    for (int64_t id = 0; id < s->n0 && ng_len(s, id) <= 1; ++id)
+        if (ng_len(s, id) == 1 && !init_unit(s, id)) { s->status = OR_UNSAT; return; }
+    for (int64_t id = s->n0; id < s->n0 + s->n_learned; ++id) {
+        if (ng_len(s, id) == 0) { s->status = OR_UNSAT; return; }
+        if (ng_len(s, id) == 1 && !init_unit(s, id)) { s->status = OR_UNSAT; return; }
     }
     qsort(s->frontier.a, (size_t)s->frontier.n, sizeof(int32_t), cmp_i32);
     s->clock += 1;
@@ -594,6 +628,26 @@ static int res_learn(or_solver *s, int32_t **outN, int64_t *outn, int32_t *outbj
 
 /* S6 + S7: Fwd-learning (Alg. 4) -- or Res-learning (Alg. 3) -- followed by
  * Backjump and assertion. */
+/* Restart: every variable is unassigned, the learned nogoods stay, and
+ * InitialPropagation runs next. */
+static void restart(or_solver *s) {
+    const int32_t W = s->W;
+    for (int32_t v = 1; v <= s->V; ++v) {
+        s->val[v] = 0;
+        s->lvl[v] = 0;
+        memset(s->deps + (size_t)v * W, 0, sizeof(uint64_t) * W);
+    }
+    s->nass = 0;
+    s->cdl = 1;
+    s->frontier.n = 0;
+    s->pend_kind = 0;
+    s->pend_id = -1;
+    s->need_init = 1;
+    s->since_restart = 0;
+    s->st.restarts += 1;
+    fnv(s, 9);
+}
+
 static void step_learn(or_solver *s, const or_limits *lim) {
     const int32_t W = s->W;
     uint64_t *B = s->pend_B;
@@ -672,6 +726,12 @@ static void step_learn(or_solver *s, const or_limits *lim) {
     s->st.learned += 1;
     s->st.learned_len += nN;
     fnv(s, 2); fnv(s, s->pend_kind == 1 ? s->pend_id : -1); fnv(s, (int32_t)nN); fnv(s, bj);
+    s->since_restart += 1;
+    if (s->restart_every > 0 && s->since_restart >= s->restart_every) {
+        free(N);
+        restart(s);
+        return;
+    }
     /* Backjump: unassign everything above bj */
     for (int32_t v = 1; v <= s->V; ++v)
         if (s->lvl[v] > bj) {
@@ -772,7 +832,7 @@ static void step_complete(or_solver *s) {
 
 /* S10: M = true original atoms; M is an answer set iff M equals the least
  * model of the reduct (rules whose body- misses M, with body- deleted). */
-static void step_gate(or_solver *s) {
+static void step_gate(or_solver *s, const or_limits *lim) {
     const int32_t A = s->A, W = s->W;
     at_fixpoint(s);
     for (int32_t p = 1; p <= A; ++p) { s->inM[p] = s->val[p] == 1; s->inLM[p] = 0; }
@@ -788,7 +848,36 @@ static void step_gate(or_solver *s) {
     int32_t u = 0;
     for (int32_t p = 1; p <= A && !u; ++p)
         if (s->inM[p] && !s->inLM[p]) u = p;
-    if (!u) { s->status = OR_SAT; return; }
+    if (!u) {
+        /* M is an answer set */
+        if (s->st.models == s->models_cap) {
+            s->models_cap = s->models_cap ? 2 * s->models_cap : 4;
+            s->models = (uint8_t *)realloc(s->models, (size_t)(s->models_cap * (A > 0 ? A : 1)));
+        }
+        for (int32_t p = 1; p <= A; ++p) s->models[s->st.models * A + p - 1] = (uint8_t)s->inM[p];
+        s->st.models += 1;
+        if (s->max_models == 1) { s->status = OR_SAT; return; }
+        fnv(s, 8); fnv(s, (int32_t)s->st.models);
+        if (s->max_models > 0 && s->st.models >= s->max_models) { s->status = OR_SAT; return; }
+        /* block M by {T p : p in M}, then restart */
+        int32_t n = 0;
+        for (int32_t p = 1; p <= A; ++p) n += s->inM[p];
+        if ((lim && lim->learned_cap_ng >= 0 && s->n_learned + 1 > lim->learned_cap_ng) ||
+            (lim && lim->learned_cap_lits >= 0 && s->learned_lits + n > lim->learned_cap_lits)) {
+            s->status = OR_UNKNOWN;
+            return;
+        }
+        int32_t *N = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        n = 0;
+        for (int32_t p = 1; p <= A; ++p)
+            if (s->inM[p]) N[n++] = p;
+        add_nogood(s, N, n);
+        free(N);
+        s->n_learned += 1;
+        s->learned_lits += n;
+        restart(s);
+        return;
+    }
     s->st.gate_failures += 1;
     uint64_t *B = s->pend_B;
     memset(B, 0, sizeof(uint64_t) * W);
@@ -823,7 +912,7 @@ static void step_gate(or_solver *s) {
 static int32_t next_step(or_solver *s, int32_t *j) {
     *j = -1;
     if (s->status != OR_RUNNING) return ST_DONE;
-    if (s->last_step == ST_NONE) return ST_INIT;
+    if (s->need_init) return ST_INIT;
     if (s->pend_kind) return ST_LEARN;
     if (s->frontier.n > 0) return ST_ROUND;
     if (s->nass == s->V) return ST_GATE;
@@ -845,10 +934,15 @@ int32_t or_step(void *h, const or_limits *lim) {
     case ST_LEARN: step_learn(s, lim); break;
     case ST_DECIDE: step_decide(s, j); break;
     case ST_COMPLETE: step_complete(s); break;
-    case ST_GATE: step_gate(s); break;
+    case ST_GATE: step_gate(s, lim); break;
     default: return s->status;
     }
     s->last_step = k;
+    if ((s->status == OR_UNSAT || s->status == OR_UNKNOWN) && s->st.models > 0) {
+        /* the search ended after answer sets were found */
+        s->exhausted = s->status == OR_UNSAT;
+        s->status = OR_SAT;
+    }
     if (s->status == OR_SAT) fnv(s, 4);
     else if (s->status == OR_UNSAT) fnv(s, 5);
     else if (s->status == OR_UNKNOWN) fnv(s, 6);
@@ -865,13 +959,13 @@ int32_t or_run(void *h, const or_limits *lim, int64_t max_steps) {
 
 /* dims: [V, A, Rh, n_static_nogoods, static_lits, W, cdl, frontier size,
  *        n_learned, learned_lits, pending kind, pending id, status, last step,
- *        constraints kept] */
+ *        constraints kept, answer sets exhausted] */
 void or_dims(void *h, int64_t *d) {
     or_solver *s = (or_solver *)h;
     d[0] = s->V; d[1] = s->A; d[2] = s->Rh; d[3] = s->n0; d[4] = s->lits0;
     d[5] = s->W; d[6] = s->cdl; d[7] = s->frontier.n; d[8] = s->n_learned;
     d[9] = s->learned_lits; d[10] = s->pend_kind; d[11] = s->pend_id;
-    d[12] = s->status; d[13] = s->last_step; d[14] = s->Rc;
+    d[12] = s->status; d[13] = s->last_step; d[14] = s->Rc; d[15] = s->exhausted;
 }
 
 /* all nogoods (static then learned) as CSR */
@@ -906,6 +1000,26 @@ int32_t or_set_learning(void *h, int32_t mode) {
     return 0;
 }
 
+/* Ask for up to max_models answer sets (0: all; 1, the default, is the plain
+ * search) and restart every restart_every conflicts (0: never), before the
+ * first step.  Returns 0, or OR_E_INVALID. */
+int32_t or_set_enum(void *h, int64_t max_models, int64_t restart_every) {
+    or_solver *s = (or_solver *)h;
+    if (s->last_step != ST_NONE || max_models < 0 || restart_every < 0) return OR_E_INVALID;
+    s->max_models = max_models;
+    s->restart_every = restart_every;
+    return 0;
+}
+
+/* the answer sets found so far: out[k*A + p-1] = 1 iff atom p is true in
+ * the k-th (at most max_out of them); returns how many were found */
+int64_t or_models(void *h, uint8_t *out, int64_t max_out) {
+    or_solver *s = (or_solver *)h;
+    int64_t n = s->st.models < max_out ? s->st.models : max_out;
+    if (n > 0) memcpy(out, s->models, (size_t)(n * s->A));
+    return s->st.models;
+}
+
 /* 1 while the supplied scores drive Decision, 0 after the fallback (or when
  * none were supplied); *consec gets the current run of conflicts */
 int32_t or_score_mode(void *h, int32_t *consec) {
@@ -934,9 +1048,14 @@ void or_state(void *h, int8_t *val, int32_t *lvl, uint64_t *deps, int32_t *dec,
 
 void or_get_stats(void *h, or_stats *out) { *out = ((or_solver *)h)->st; }
 
-/* model over original atoms: model[p-1] = 1 iff p is true */
+/* model over original atoms: model[p-1] = 1 iff p is true in the first
+ * answer set found (before one is found: in the current assignment) */
 void or_model(void *h, uint8_t *model) {
     or_solver *s = (or_solver *)h;
+    if (s->st.models > 0) {
+        memcpy(model, s->models, (size_t)s->A);
+        return;
+    }
     for (int32_t p = 1; p <= s->A; ++p) model[p - 1] = s->val[p] == 1;
 }
 
@@ -945,12 +1064,15 @@ int32_t or_solve(int32_t n_atoms, int32_t n_rules, const int32_t *head,
                  const int64_t *body_off, const int32_t *body_lits, int32_t W,
                  int32_t gate_mode, const or_limits *lim, uint8_t *model,
                  or_stats *st, const int32_t *score, int32_t fallback_after,
-                 int32_t learning) {
+                 int32_t learning, int64_t max_models, int64_t restart_every) {
     int32_t err = 0;
     void *h = or_create(n_atoms, n_rules, head, body_off, body_lits, W, gate_mode, &err);
     if (!h) return err;
     if (score) or_set_scores(h, score, fallback_after);
-    if (or_set_learning(h, learning) != 0) { or_free(h); return OR_E_INVALID; }
+    if (or_set_learning(h, learning) != 0 || or_set_enum(h, max_models, restart_every) != 0) {
+        or_free(h);
+        return OR_E_INVALID;
+    }
     int32_t rc = or_run(h, lim, -1);
     if (model && rc == OR_SAT) or_model(h, model);
     if (st) or_get_stats(h, st);

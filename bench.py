@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-steps", type=int, default=2)
     ap.add_argument("--no-res", action="store_true", help="skip the Res-learning leg")
+    ap.add_argument("--no-enum", action="store_true", help="skip the several-answer-sets leg")
+    ap.add_argument("--enum-models", type=int, default=16, help="answer sets asked per program")
     ap.add_argument("--res-steps", type=int, default=2)
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="replays of the batched solve as one HIP graph, timed after the eager steps")
@@ -401,6 +403,9 @@ def main():
     if not args.no_res:
         log("[bench] Res-learning leg")
         line["res"] = res_leg(args, P, progs, verd, stream, dev, lim, ms_step, cth)
+    if not args.no_enum:
+        log("[bench] several-answer-sets leg")
+        line["enum"] = enum_leg(args, P, progs, verd, stream, dev, lim, cth)
     if not args.no_learned:
         log("[bench] learned Decision leg")
         line["learned"] = learned_leg(args, P, progs, verd, stream, dev, lim, ms_step, cth)
@@ -439,6 +444,51 @@ def res_leg(args, P, progs, fwd_verd, stream, dev, lim, fwd_ms_step, cth):
         "literal_checks_per_s": sum(int(s["literal_checks"]) for s in stats) / (ms_step / 1000.0),
         "counters": search_counters(stats, ms_step),
         "time_split": time_split(stats),
+        "instance_ms": tail(stats),
+    }
+    del batch
+    torch.cuda.empty_cache()
+    return out
+
+
+def enum_leg(args, P, progs, plain_verd, stream, dev, lim, cth):
+    """The same batch, budget and schedule asking for up to --enum-models
+    answer sets per program (blocking nogood and restart after each)."""
+    import torch
+    k = args.enum_models
+    gp = load_programs(progs, args.W, args.cap_ng, args.cap_lits, max_models=k)
+    batch = P.Batch(gp, threads=args.threads, classes=args.classes, class_threads=cth)
+    with torch.cuda.stream(stream):
+        batch.bind(dev, stream=stream)
+    torch.cuda.synchronize()
+    ms, walls = timed_steps(batch, lim, 1, 1)
+    verd, models, stats = batch.results(all_models=True)
+    ms_step = float(np.sum(walls)) * 1000.0 / len(walls)
+    found = np.array([int(s["models"]) for s in stats])
+    exhausted = np.array([int(s["exhausted"]) for s in stats])
+    contra = int(((found > 0) & (plain_verd == 2)).sum() + ((found == 0) & (plain_verd == 1)).sum())
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from judge import is_stable
+    n_checked = bad = dup = 0
+    for i in np.nonzero(found > 0)[0]:
+        ms_i = models[i]
+        dup += len(ms_i) - len({m.tobytes() for m in ms_i})
+        for m in ms_i:
+            n_checked += 1
+            bad += 0 if is_stable(progs[i], m) else 1
+    out = {
+        "max_models": k, "ms_per_step": ms_step,
+        "answer_sets_per_s": float(found.sum()) / (ms_step / 1000.0),
+        "answer_sets": int(found.sum()),
+        "instances_with_answer_sets": int((found > 0).sum()),
+        "instances_at_max_models": int((found >= k).sum()),
+        "instances_exhausted": int(exhausted.sum()),
+        "unsat": int((verd == 2).sum()), "unknown": int((verd == 3).sum()),
+        "error": int((verd < 0).sum()),
+        "restarts": int(sum(int(s["restarts"]) for s in stats)),
+        "verdict_contradictions_vs_plain": contra,
+        "answer_sets_verified": {"checked": n_checked, "not_stable": bad, "duplicates": dup},
+        "counters": search_counters(stats, ms_step),
         "instance_ms": tail(stats),
     }
     del batch

@@ -102,7 +102,24 @@ typedef struct {
                                   heuristic takes over for the rest of the
                                   search; < 0 never.  Default 10 */
     int32_t learning;          /* ASP_LEARN_FWD (default) or ASP_LEARN_RES */
-    int32_t reserved;
+    int32_t reserved;          /* 0 */
+    int64_t max_models;        /* answer sets asked for (the paper restarts the
+                                  solver when more than one solution is
+                                  requested, Sect. 3): 1 (default) is the
+                                  plain search; k > 1 finds up to k; 0 finds
+                                  all.  After an answer set M the search
+                                  learns {T p : p in M} (answer sets are
+                                  incomparable under inclusion, so this
+                                  excludes M alone) and restarts: everything
+                                  is unassigned, learned nogoods stay, and
+                                  InitialPropagation also takes the learned
+                                  unit nogoods.  The first max(1, max_models)
+                                  answer sets are kept (n_atoms bytes each) */
+    int64_t restart_every;     /* > 0: a conflict that makes this many
+                                  conflicts since the last restart learns its
+                                  nogood and restarts instead of backjumping
+                                  (the paper's restart option, Sect. 3);
+                                  0 (default) never */
 } asp_options;
 
 /* Run limits. */
@@ -139,6 +156,13 @@ typedef struct {
     int64_t ns_total;          /* device time of the solve (solve calls only) */
     int64_t ns_round, ns_learn, ns_decide, ns_gate;  /* split by step kind;
                                   ns_decide includes CompleteAssignment */
+    int64_t models;            /* answer sets found */
+    int64_t restarts;          /* restarts (after answer sets and by
+                                  restart_every) */
+    int32_t exhausted;         /* 1: the search showed no further answer set
+                                  exists (the status is then ASP_SAT if one
+                                  was found) */
+    int32_t reserved;
 } asp_stats;
 
 typedef struct {
@@ -194,7 +218,7 @@ typedef struct {
  *  body_lits  : +a (atom a) or -a (not a), 1 <= a <= n_atoms
  *  opt        : NULL = {W=1, gate=UNFOUNDED, learned_cap_ng=1<<20,
  *               learned_cap_lits=1<<22, decision=OCC, fallback_after=10,
- *               learning=FWD}
+ *               learning=FWD, max_models=1, restart_every=0}
  * Repeated body literals are removed (first kept); a constraint holding both
  * a and not a is dropped.  Nogoods are generated per headed rule, then per
  * atom, then per constraint, and stably sorted by length (Sect. 4); their
@@ -256,11 +280,23 @@ int32_t asp_get_scores(asp_program *prog, int32_t *scores, void *stream);
 int32_t asp_run_steps(asp_program *prog, void *stream, const asp_limits *lim,
                       int64_t n_steps, asp_stats *stats);
 
-/* Solve from scratch to the first answer set.  model (optional, n_atoms
- * bytes, host) gets 1 for the true atoms when the result is ASP_SAT.
- * Returns ASP_SAT, ASP_UNSAT, ASP_UNKNOWN or an error.  Synchronous. */
+/* Solve from scratch (to the first answer set, or to max_models of them).
+ * model (optional, n_atoms bytes, host) gets 1 for the true atoms of the
+ * first answer set when the result is ASP_SAT.  A search that ends UNSAT or
+ * UNKNOWN after finding answer sets reports ASP_SAT (stats.exhausted tells
+ * whether no further one exists).  Returns ASP_SAT, ASP_UNSAT, ASP_UNKNOWN
+ * or an error.  Synchronous. */
 int32_t asp_solve(asp_program *prog, void *stream, const asp_limits *lim,
                   uint8_t *model, asp_stats *stats);
+
+/* The answer sets found by the last search of a bound program, in the order
+ * found: models (host, max_out * n_atoms bytes) gets the first
+ * min(found, max(1, max_models), max_out), answer set k at k * n_atoms;
+ * *found (optional) the number found.  Errors: ASP_E_STATE if unbound,
+ * ASP_E_INVALID for max_out < 0 or a NULL buffer with max_out > 0.
+ * Synchronous. */
+int32_t asp_get_models(asp_program *prog, void *stream, uint8_t *models, int64_t max_out,
+                       int64_t *found);
 
 /* State export: with st->val == NULL only the scalars are filled (to size
  * the arrays); otherwise every non-NULL array is filled as well. */
@@ -268,7 +304,8 @@ int32_t asp_state_export(asp_program *prog, void *stream, asp_state *st);
 
 /* State import (the frontier must hold variables of level cdl; the pending
  * field may name a round conflict; learned nogoods must hold decision
- * literals T b_r only).  Fwd-learning programs only.  Errors: ASP_E_INVALID
+ * literals T b_r only).  Fwd-learning programs with max_models = 1 and no
+ * restarts only.  Errors: ASP_E_INVALID
  * on inconsistent input, ASP_E_CAPACITY beyond the learned-store capacity. */
 int32_t asp_state_import(asp_program *prog, void *stream, const asp_state *st);
 
@@ -280,7 +317,8 @@ int32_t asp_state_import(asp_program *prog, void *stream, const asp_state *st);
  * programs must stay alive until asp_batch_bind returns.
  * sched: NULL = {128 threads, 4 classes}.  *device_bytes gets the arena
  * size; *model_bytes (optional) the size of the model output, which holds
- * instance i's n_atoms bytes after those of instances 0..i-1. */
+ * instance i's max(1, max_models) answer sets of n_atoms bytes each after
+ * those of instances 0..i-1. */
 int32_t asp_batch_create(int32_t n, asp_program *const *progs,
                          const asp_schedule *sched, asp_batch **out,
                          uint64_t *device_bytes, uint64_t *model_bytes);

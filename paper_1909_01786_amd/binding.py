@@ -33,7 +33,8 @@ class AspError(RuntimeError):
 class asp_options(C.Structure):
     _fields_ = [("W", C.c_int32), ("gate", C.c_int32), ("learned_cap_ng", C.c_int64),
                 ("learned_cap_lits", C.c_int64), ("decision", C.c_int32),
-                ("fallback_after", C.c_int32), ("learning", C.c_int32), ("reserved", C.c_int32)]
+                ("fallback_after", C.c_int32), ("learning", C.c_int32), ("reserved", C.c_int32),
+                ("max_models", C.c_int64), ("restart_every", C.c_int64)]
 
 
 class asp_limits(C.Structure):
@@ -52,7 +53,9 @@ _STAT_NAMES = ("rounds", "visits", "literal_checks", "propagations", "decisions"
 class asp_stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in _STAT_NAMES] + [
         ("trace_hash", C.c_uint64), ("status", C.c_int32), ("last_step", C.c_int32)] + [
-        (n, C.c_int64) for n in ("ns_total", "ns_round", "ns_learn", "ns_decide", "ns_gate")]
+        (n, C.c_int64) for n in ("ns_total", "ns_round", "ns_learn", "ns_decide", "ns_gate")] + [
+        ("models", C.c_int64), ("restarts", C.c_int64), ("exhausted", C.c_int32),
+        ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -132,6 +135,7 @@ EXPORTS = (
     "asp_batch_set_scores", "asp_batch_get_scores", "asp_scorer_workspace",
     "asp_batch_scorer_workspace", "asp_score_program", "asp_score_batch",
     "asp_batch_train_readout", "asp_batch_launch_info", "asp_solve_batch_graph",
+    "asp_get_models",
 )
 
 _lib = None
@@ -156,6 +160,7 @@ def lib():
                                            C.POINTER(i32)]),
             "asp_run_steps": (i32, [P, P, C.POINTER(asp_limits), i64, C.POINTER(asp_stats)]),
             "asp_solve": (i32, [P, P, C.POINTER(asp_limits), P, C.POINTER(asp_stats)]),
+            "asp_get_models": (i32, [P, P, P, i64, C.POINTER(i64)]),
             "asp_state_export": (i32, [P, P, C.POINTER(asp_state)]),
             "asp_state_import": (i32, [P, P, C.POINTER(asp_state)]),
             "asp_batch_create": (i32, [i32, P, C.POINTER(asp_schedule), C.POINTER(P),
@@ -225,9 +230,11 @@ def limits(max_conflicts: int = -1, max_ms: int = 0) -> asp_limits:
 
 def options(W: int = 1, gate: int = GATE_UNFOUNDED, learned_cap_ng: int = 1 << 20,
             learned_cap_lits: int = 1 << 22, decision: int = DECISION_OCC,
-            fallback_after: int = 10, learning: int = LEARN_FWD) -> asp_options:
+            fallback_after: int = 10, learning: int = LEARN_FWD, max_models: int = 1,
+            restart_every: int = 0) -> asp_options:
     return asp_options(int(W), int(gate), int(learned_cap_ng), int(learned_cap_lits),
-                       int(decision), int(fallback_after), int(learning), 0)
+                       int(decision), int(fallback_after), int(learning), 0, int(max_models),
+                       int(restart_every))
 
 
 @dataclass
@@ -257,12 +264,12 @@ class Program:
     def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED,
                  learned_cap_ng: int = 1 << 20, learned_cap_lits: int = 1 << 22,
                  decision: int = DECISION_OCC, fallback_after: int = 10,
-                 learning: int = LEARN_FWD):
+                 learning: int = LEARN_FWD, max_models: int = 1, restart_every: int = 0):
         self._head = np.ascontiguousarray(prog.head, np.int32)
         self._off = np.ascontiguousarray(prog.body_off, np.int64)
         self._lits = np.ascontiguousarray(prog.body_lits, np.int32)
         self.opt = options(W, gate, learned_cap_ng, learned_cap_lits, decision, fallback_after,
-                           learning)
+                           learning, max_models, restart_every)
         self.sizes = asp_sizes()
         h = C.c_void_p()
         _check(lib().asp_load_program(int(prog.n_atoms), int(self._head.shape[0]),
@@ -348,6 +355,17 @@ class Program:
         st = _check(lib().asp_solve(self._h, _stream_ptr(self.stream),
                                     C.byref(lim) if lim else None, _ptr(m), C.byref(s)))
         return st, (m[:self.n_atoms].copy() if st == SAT else None), s.as_dict()
+
+    def models(self) -> list:
+        """The answer sets kept from the last search, in the order found
+        (at most max(1, max_models) of them)."""
+        store = max(1, int(self.opt.max_models))
+        found = C.c_int64(0)
+        buf = np.zeros(max(store * self.n_atoms, 1), np.uint8)
+        _check(lib().asp_get_models(self._h, _stream_ptr(self.stream), _ptr(buf), store,
+                                    C.byref(found)))
+        n = min(int(found.value), store)
+        return [buf[k * self.n_atoms:(k + 1) * self.n_atoms].copy() for k in range(n)]
 
     def export_state(self) -> State:
         st = asp_state()
@@ -491,15 +509,24 @@ class Batch:
         _check(lib().asp_batch_last_ms(self._h, C.byref(ms)))
         return float(ms.value)
 
-    def results(self):
+    def results(self, all_models: bool = False):
+        """(verdicts, models, stats): models[i] is instance i's first answer
+        set, or with all_models the list of the answer sets it kept."""
         n = len(self.programs)
         verd = np.zeros(n, np.int32)
         models = np.zeros(max(self.model_bytes, 1), np.uint8)
         stats = (asp_stats * n)()
         _check(lib().asp_batch_results(self._h, _stream_ptr(self.stream), _ptr(verd),
                                        _ptr(models), C.cast(stats, C.c_void_p)))
+        sd = [s.as_dict() for s in stats]
         out_models, o = [], 0
-        for p in self.programs:
-            out_models.append(models[o:o + p.n_atoms].copy())
-            o += p.n_atoms
-        return verd, out_models, [s.as_dict() for s in stats]
+        for i, p in enumerate(self.programs):
+            store = max(1, int(p.opt.max_models))
+            A = p.n_atoms
+            if all_models:
+                k = min(int(sd[i]["models"]), store)
+                out_models.append([models[o + j * A:o + (j + 1) * A].copy() for j in range(k)])
+            else:
+                out_models.append(models[o:o + A].copy())
+            o += A * store
+        return verd, out_models, sd

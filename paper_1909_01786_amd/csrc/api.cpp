@@ -24,7 +24,7 @@ namespace asp {
 size_t lds_bytes(int threads, int words);
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s);
 hipError_t set_max_lds(int threads, size_t lds);
-hipError_t occupancy(int threads, int learning, size_t lds, int* blocks_per_cu);
+hipError_t occupancy(int threads, int learning, int en, size_t lds, int* blocks_per_cu);
 }  // namespace asp
 
 using namespace asp;
@@ -87,6 +87,7 @@ struct LaunchClass {
 struct Plan {
     int32_t n = 0, threads = 256, W = 1, gate = 0, decision = 0, fallback_after = 10, learning = 0;
     int64_t Vmax = 0, Rhmax = 0, cap_ng = 0, cap_lits = 0;
+    int64_t max_models = 1, restart_every = 0, model_store = 1;
     std::vector<LaunchClass> classes;
     std::vector<InstDesc> desc;
     std::vector<int32_t> order;
@@ -166,6 +167,9 @@ asp_options default_options() {
     o.decision = ASP_DECISION_OCC;
     o.fallback_after = 10;
     o.learning = ASP_LEARN_FWD;
+    o.reserved = 0;
+    o.max_models = 1;
+    o.restart_every = 0;
     return o;
 }
 
@@ -192,6 +196,9 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.learning = opt.learning;
     P.cap_ng = opt.learned_cap_ng;
     P.cap_lits = opt.learned_cap_lits;
+    P.max_models = opt.max_models;
+    P.restart_every = opt.restart_every;
+    P.model_store = opt.max_models > 0 ? opt.max_models : 1;
     P.desc.resize(P.n);
     P.slot_off.resize(P.n);
     for (int32_t i = 0; i < P.n; ++i) {
@@ -223,7 +230,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
         P.tot_rules += (int64_t)h.rule_head.size();
         P.tot_rbo += (int64_t)h.rb_off.size();
         P.tot_rbl += (int64_t)h.rb_lits.size();
-        P.tot_model += h.A;
+        P.tot_model += (int64_t)h.A * P.model_store;
         P.tot_asc += (int64_t)h.A + 1;
         P.Vmax = std::max<int64_t>(P.Vmax, h.V);
         P.Rhmax = std::max<int64_t>(P.Rhmax, h.Rh);
@@ -351,6 +358,9 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& 
     a.decision = P.decision;
     a.fallback_after = P.fallback_after;
     a.learning = P.learning;
+    a.max_models = P.max_models;
+    a.restart_every = P.restart_every;
+    a.model_store = P.model_store;
     a.words = lc.words;
     a.step_mask = 0;
     a.max_steps = -1;
@@ -365,9 +375,10 @@ void apply_limits(KArgs& a, const Plan& P, const asp_limits* lim, const DeviceIn
     a.max_conflicts = lim ? lim->max_conflicts : -1;
     int64_t ms = (lim && lim->max_ms > 0) ? lim->max_ms : kDefaultMaxMs;
     a.max_ticks = di.clock_khz > 0 ? (uint64_t)ms * (uint64_t)di.clock_khz : 0;
-    // step guard: between two conflicts a search runs at most 3V + 4 steps
-    if (a.max_conflicts >= 0)
-        a.max_steps = (a.max_conflicts + 2) * (3 * P.Vmax + P.Rhmax + 16) + 16;
+    // step guard: between two conflicts, or two answer sets, a search runs at
+    // most 3V + 4 steps (no guard when every answer set is asked for)
+    if (a.max_conflicts >= 0 && P.max_models > 0)
+        a.max_steps = (a.max_conflicts + P.max_models + 2) * (3 * P.Vmax + P.Rhmax + 16) + 16;
     else
         a.max_steps = -1;
 }
@@ -391,6 +402,10 @@ void to_stats(const DevStats& d, asp_stats* s) {
     s->trace_hash = d.hash;
     s->status = d.status;
     s->last_step = d.last_step;
+    s->models = d.models;
+    s->restarts = d.restarts;
+    s->exhausted = d.exhausted;
+    s->reserved = 0;
     s->ns_total = ticks_ns(d.t_total);
     s->ns_round = ticks_ns(d.t_round);
     s->ns_learn = ticks_ns(d.t_learn);
@@ -413,6 +428,10 @@ void ctrl_stats(const SlotCtrl& k, asp_stats* s) {
     s->status = k.status;
     s->last_step = k.last_step;
     s->ns_total = s->ns_round = s->ns_learn = s->ns_decide = s->ns_gate = 0;
+    s->models = k.models;
+    s->restarts = k.restarts;
+    s->exhausted = k.exhausted;
+    s->reserved = 0;
 }
 
 int32_t check_launch(const Plan& P, const DeviceInfo& di) {
@@ -674,6 +693,10 @@ int32_t asp_load_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
         return fail(ASP_E_INVALID, "unknown decision heuristic");
     if (o.learning != ASP_LEARN_FWD && o.learning != ASP_LEARN_RES)
         return fail(ASP_E_INVALID, "unknown learning step");
+    if (o.max_models < 0 || o.max_models > ((int64_t)1 << 30) || o.restart_every < 0)
+        return fail(ASP_E_INVALID, "max_models must be in 0..2^30, restart_every >= 0");
+    if ((int64_t)n_atoms * (o.max_models > 0 ? o.max_models : 1) > ((int64_t)1 << 34))
+        return fail(ASP_E_INVALID, "answer-set store beyond 2^34 bytes");
     std::unique_ptr<asp_program> p(new asp_program());
     std::string err;
     int rc = encode_program(n_atoms, n_rules, head, body_off, body_lits, &p->hp, &err);
@@ -870,6 +893,23 @@ int32_t asp_solve(asp_program* p, void* stream, const asp_limits* lim, uint8_t* 
     return verdict;
 }
 
+int32_t asp_get_models(asp_program* p, void* stream, uint8_t* models, int64_t max_out,
+                       int64_t* found) {
+    if (!p || !p->bound) return fail(ASP_E_STATE, "program not bound to a device arena");
+    if (max_out < 0 || (max_out > 0 && !models)) return fail(ASP_E_INVALID, "bad output buffer");
+    hipStream_t s = (hipStream_t)stream;
+    SlotCtrl k;
+    int32_t rc = read_ctrl(p, s, &k);
+    if (rc) return rc;
+    const int64_t n = std::min(std::min(k.models, p->plan.model_store), max_out);
+    if (n > 0 && p->hp.A > 0)
+        HIPCHK(hipMemcpyAsync(models, p->arena + p->plan.off_models, (size_t)(n * p->hp.A),
+                              hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (found) *found = k.models;
+    return ASP_OK;
+}
+
 int32_t asp_state_export(asp_program* p, void* stream, asp_state* st) {
     if (!p || !p->bound || !st) return fail(ASP_E_STATE, "program not bound or null state");
     hipStream_t s = (hipStream_t)stream;
@@ -918,6 +958,9 @@ int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
     if (p->opt.learning != ASP_LEARN_FWD)
         return fail(ASP_E_INVALID, "state import needs assignment stamps and reasons that "
                                    "Res-learning programs keep on the device only");
+    if (p->opt.max_models != 1 || p->opt.restart_every != 0)
+        return fail(ASP_E_INVALID, "state import is for the plain search (one answer set, "
+                                   "no restarts)");
     const int32_t V = p->hp.V, W = p->opt.W, A = p->hp.A, Rh = p->hp.Rh;
     const int32_t nS = (int32_t)p->hp.n_nogoods();
     if (st->n_vars != V || st->W != W) return fail(ASP_E_INVALID, "state shape mismatch");
@@ -1077,7 +1120,8 @@ int32_t asp_batch_create(int32_t n, asp_program* const* progs, const asp_schedul
         const asp_options& o = progs[i]->opt;
         if (o.W != b->opt.W || o.gate != b->opt.gate || o.learned_cap_ng != b->opt.learned_cap_ng ||
             o.learned_cap_lits != b->opt.learned_cap_lits || o.decision != b->opt.decision ||
-            o.fallback_after != b->opt.fallback_after || o.learning != b->opt.learning)
+            o.fallback_after != b->opt.fallback_after || o.learning != b->opt.learning ||
+            o.max_models != b->opt.max_models || o.restart_every != b->opt.restart_every)
             return fail(ASP_E_INVALID, "batch programs must share their options");
         b->progs.push_back(&progs[i]->hp);
     }

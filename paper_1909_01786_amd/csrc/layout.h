@@ -39,7 +39,8 @@ struct InstDesc {
     int64_t rules;     // into rule_head[] / rule_occ[] (Rh entries)
     int64_t rb_off;    // into rb_off[] (Rh+1 entries, values relative to rb_lits)
     int64_t rb_lits;   // into rb_lits[] (rule bodies, +a body+ / -a body-)
-    int64_t model;     // byte offset of this instance's model in models[]
+    int64_t model;     // byte offset of this instance's answer sets in models[]
+                       // (model_store of them, A bytes each)
     int64_t ascore;    // into atom_score[] (A+1 entries, [0] unused)
     int32_t A, Rh, V, n_static;
     int32_t u0, u1;    // ids of the unit nogoods: [u0, u1)
@@ -54,8 +55,9 @@ struct SlotCtrl {
     int32_t n_learned, pool_top, pending, pend_kind;  // pend_kind 0 none, 1 round, 2 gate
     int32_t status, init_done, last_step, use_score;
     int32_t consec, dec_open;                // learned-Decision fallback state
-    int32_t epoch, pad_e;                    // resolution marks
+    int32_t epoch, exhausted;                // resolution marks; no answer set left
     int64_t learned_lits;
+    int64_t models, restarts, since_restart; // answer sets found, restarts
     int64_t rounds, visits, checks, props, decisions, conflicts, learned, learned_len,
             gate_fail, completes;
     uint64_t hash;
@@ -128,6 +130,8 @@ struct DevStats {
     uint64_t hash;
     int32_t status, last_step;
     uint64_t t_total, t_round, t_learn, t_decide, t_gate;   // wall-clock ticks
+    int64_t models, restarts;
+    int32_t exhausted, pad;
 };
 
 enum StepKind : int32_t {
@@ -181,6 +185,9 @@ struct KArgs {
     int64_t max_conflicts;       // <0 unlimited
     int64_t cap_ng, cap_lits;
     uint64_t max_ticks;          // wall-clock guard in s_memrealtime ticks, 0 none
+    int64_t max_models;          // answer sets asked for; 0 all, 1 the plain search
+    int64_t restart_every;       // conflicts between restarts; 0 never
+    int64_t model_store;         // answer sets kept per instance (n_atoms bytes each)
 };
 
 }  // namespace asp

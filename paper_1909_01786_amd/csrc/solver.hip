@@ -62,8 +62,10 @@ struct Ctl {
     int32_t use_score, consec, dec_open;   // score-driven Decision and its fallback
     int32_t fr_ok;    // the LDS records describe the frontier trail[qh..qt)
     int32_t epoch;          // resolution-mark epoch (Res-learning)
+    int32_t exhausted;      // the search showed no further answer set exists
     int64_t learned_lits, rounds, props, decisions, conflicts, learned, learned_len, gate_fail,
             completes, steps, visits, checks;
+    int64_t models, restarts, since_restart;
     uint64_t hash;
     // device time per step kind (wall-clock ticks; read per wave, so the
     // copies of different waves may differ -- timing only, never control)
@@ -112,6 +114,7 @@ struct Ctx {
     Scr* scr;
     int32_t W, T, tid, lane, wid, nw;
     int32_t decision, fallback_after, learning;
+    int32_t enumerate;      // several answer sets or restarts (compile-time in k_search)
     unsigned long long my_visits, my_checks;
 };
 
@@ -391,6 +394,8 @@ DEV void reset_search(Ctx& c, Ctl& k) {
     k.t_round = k.t_learn = k.t_decide = k.t_gate = 0;
     k.fr_ok = 0;
     k.epoch = 0;
+    k.exhausted = 0;
+    k.models = k.restarts = k.since_restart = 0;
     tab_clear_all(c);
     bar();
 }
@@ -438,6 +443,10 @@ DEV void load_ctrl(Ctx& c, Ctl& k) {
     k.consec = uni(g.consec);
     k.dec_open = uni(g.dec_open);
     k.epoch = uni(g.epoch);
+    k.exhausted = uni(g.exhausted);
+    k.models = uni64(g.models);
+    k.restarts = uni64(g.restarts);
+    k.since_restart = uni64(g.since_restart);
     k.steps = 0;
     k.t_round = k.t_learn = k.t_decide = k.t_gate = 0;
     k.fr_ok = 0;
@@ -489,20 +498,35 @@ DEV void save_ctrl(Ctx& c, const Ctl& k) {
     g.consec = k.consec;
     g.dec_open = k.dec_open;
     g.epoch = k.epoch;
+    g.exhausted = k.exhausted;
+    g.models = k.models;
+    g.restarts = k.restarts;
+    g.since_restart = k.since_restart;
     bar();
 }
 
 // ------------------------------------------------------------- steps
-// InitialPropagation (Alg. 1): each unit nogood {l} assigns the complement
-// of l at level 1 with empty Deps; opposite units mean no answer set.
+// InitialPropagation (Alg. 1): each unit nogood {l} -- the static ones and,
+// after a restart, the learned ones -- assigns the complement of l at level
+// 1 with empty Deps; opposite units, or an empty learned nogood, mean no
+// answer set.
 DEV void step_init(Ctx& c, Ctl& k) {
     const int T = c.T, tid = c.tid;
     c.scr->clash = k.has_empty;
     c.scr->tail = k.qt;
     bar();
     if (!k.has_empty) {
-        for (int id = k.u0 + tid; id < k.u1; id += T) {
-            int l = c.NL[c.NO[id]];
+        const int nu = k.u1 - k.u0;
+        for (int q = tid; q < nu + k.n_learned; q += T) {
+            int l;
+            if (q < nu) {
+                l = c.NL[c.NO[k.u0 + q]];
+            } else {
+                const int o = c.loff[q - nu], len = c.loff[q - nu + 1] - o;
+                if (len == 0) c.scr->clash = 1;
+                if (len != 1) continue;
+                l = c.llits[o];
+            }
             int x = lvar(l);
             uint32_t code = l > 0 ? VF : VT;
             uint32_t sh = (uint32_t)(x & 15) << 1;
@@ -633,8 +657,9 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
             // (the map literal's variable is the frontier variable: its Deps
             // come with the frontier; a short nogood's entry holds the map
             // segment of each literal it can make true; under Fwd-learning
-            // learned occurrence lists exist only for decision literals T b_r,
-            // under Res-learning for literals of either sign)
+            // learned occurrence lists exist only for decision literals T b_r
+            // -- and, when answer sets are blocked, atoms T p -- under
+            // Res-learning for literals of either sign)
             unsigned long long d;
             int s0, cs;
             if (inl) {
@@ -653,7 +678,7 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
                 s0 = c.MO[li];
                 cs = c.MO[li + 1] - s0;
             }
-            const bool dec_lit = c.learning == LEARN_RES ||
+            const bool dec_lit = c.learning == LEARN_RES || (c.enumerate && code == VT) ||
                                  (code == VT && x > k.A && (x - k.A - 1) % 3 == 0);
             const int lli = 2 * x + (code == VF ? 1 : 0);
             const int l0 = dec_lit ? c.lptr[lli] : 0;
@@ -811,35 +836,34 @@ DEV void step_round(Ctx& c, Ctl& k) {
                 c.fDeps[i - qt] = d0;
             }
         } else {
-            const int32_t* lits;
-            int len;
-            int32_t inl[3];
-            if (lo != NO_ENTRY) {
-                // the winner is a short static nogood: its literals are in the entry
-                const MapEntry e = c.ME[lo];
-                inl[0] = e.self;
-                inl[1] = e.o1;
-                inl[2] = e.o2;
-                lits = inl;
-                len = 1 + (e.o1 != 0 ? 1 : 0) + (e.o2 != 0 ? 1 : 0);
-            } else {
-                ng_span(c, k, id, lits, len);
-            }
+            // OR of the Deps of the winner's other variables; a short static
+            // nogood's literals are in its map entry (0 marks an absent one)
+            auto each_other = [&](auto&& add) {
+                if (lo != NO_ENTRY) {
+                    const MapEntry e = c.ME[lo];
+                    add(lvar(e.self));
+                    add(lvar(e.o1));
+                    add(lvar(e.o2));
+                } else {
+                    const int32_t* lits;
+                    int len;
+                    ng_span(c, k, id, lits, len);
+                    for (int q = 0; q < len; ++q) add(lvar(lits[q]));
+                }
+            };
             if (W == 1) {
                 unsigned long long acc = 0ull;
-                for (int q = 0; q < len; ++q) {
-                    int y = lvar(lits[q]);
-                    if (y != x) acc |= c.deps[y];
-                }
+                each_other([&](int y) {
+                    if (y != 0 && y != x) acc |= c.deps[y];
+                });
                 dx[0] = acc;
             } else {
                 for (int w = 0; w < W; ++w) dx[w] = 0ull;
-                for (int q = 0; q < len; ++q) {
-                    int y = lvar(lits[q]);
-                    if (y == x) continue;
+                each_other([&](int y) {
+                    if (y == 0 || y == x) return;
                     const uint64_t* dy = c.deps + (size_t)y * W;
                     for (int w = 0; w < W; ++w) dx[w] |= dy[w];
-                }
+                });
             }
             if (rec) put_record(c, i - qt, x, code, dx[0]);
         }
@@ -1040,6 +1064,54 @@ DEV int res_learn(Ctx& c, Ctl& k, const KArgs& a, int base, int top, int* nN_out
     return 1;
 }
 
+// Literal occurrence lists of a new learned nogood llits[base..base+nN)
+// (one lane per literal; the literals are distinct): doubling arrays in the
+// slot's pool, claimed from scr->pool_top; an overflow sets scr->cap_err.
+DEV void add_occurrences(Ctx& c, int base, int nN, int newid) {
+    for (int i = c.tid; i < nN; i += c.T) {
+        int li = lidx(c.llits[base + i]);
+        int n = c.ln[li], cap = c.lcap[li], p = c.lptr[li];
+        if (n == cap) {
+            int ncap = cap ? 2 * cap : 4;
+            int np = atomicAdd(&c.scr->pool_top, ncap);
+            if ((int64_t)np + ncap > c.pool_cap) {
+                c.scr->cap_err = 1;
+                continue;
+            }
+            for (int q = 0; q < n; ++q) c.pool[np + q] = c.pool[p + q];
+            c.lptr[li] = np;
+            c.lcap[li] = ncap;
+            p = np;
+        }
+        c.pool[p + n] = newid;
+        c.ln[li] = n + 1;
+    }
+}
+
+// Restart: every assigned variable (the trail) is unassigned, the learned
+// nogoods stay, and InitialPropagation runs next.
+DEV void restart(Ctx& c, Ctl& k) {
+    const int W = c.W, T = c.T, tid = c.tid;
+    const int words = (k.V + 1 + 15) >> 4;
+    for (int i = tid; i < words; i += T) c.valb[i] = 0u;
+    for (int i = tid; i < k.qt; i += T) {
+        const int v = c.trail[i];
+        c.lvl[v] = 0;
+        for (int w = 0; w < W; ++w) c.deps[(size_t)v * W + w] = 0ull;
+    }
+    for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
+    k.cdl = 1;
+    k.qh = k.qt = 0;
+    k.pending = -1;
+    k.pend_kind = 0;
+    k.init_done = 0;
+    k.fr_ok = 0;
+    k.since_restart = 0;
+    k.restarts += 1;
+    k.hash = fnv(k.hash, 9);
+    bar();
+}
+
 // Fwd-learning (Sect. 4.2, Alg. 4) -- or Res-learning (Alg. 3) -- +
 // Backjump + assertion.
 DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
@@ -1186,25 +1258,22 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     k.hash = fnv(k.hash, bj);
     c.loff[k.n_learned + 1] = base + nN;
     bar();
-    // literal occurrence lists of the new nogood (one lane per literal; the
-    // literals are distinct): doubling arrays in the slot's pool
-    for (int i = tid; i < nN; i += T) {
-        int li = lidx(c.llits[base + i]);
-        int n = c.ln[li], cap = c.lcap[li], p = c.lptr[li];
-        if (n == cap) {
-            int ncap = cap ? 2 * cap : 4;
-            int np = atomicAdd(&c.scr->pool_top, ncap);
-            if ((int64_t)np + ncap > c.pool_cap) {
-                c.scr->cap_err = 1;
-                continue;
-            }
-            for (int q = 0; q < n; ++q) c.pool[np + q] = c.pool[p + q];
-            c.lptr[li] = np;
-            c.lcap[li] = ncap;
-            p = np;
+    add_occurrences(c, base, nN, newid);
+    k.since_restart += 1;
+    if (c.enumerate && a.restart_every > 0 && k.since_restart >= a.restart_every) {
+        bar();
+        k.pool_top = uni(c.scr->pool_top);
+        if (uni(c.scr->cap_err)) {
+            k.status = ST_E_CAPACITY;
+            bar();
+            return;
         }
-        c.pool[p + n] = newid;
-        c.ln[li] = n + 1;
+        k.n_learned += 1;
+        k.learned_lits += nN;
+        k.learned += 1;
+        k.learned_len += nN;
+        restart(c, k);
+        return;
     }
     // Backjump: unassign every variable above level bj (the trail holds
     // levels in non-decreasing order, level l starting at tlim[l])
@@ -1361,6 +1430,68 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
 // Otherwise the unfounded set U = M \ LM gives the conflict: its least atom
 // u with every external support (head in U, body+ disjoint from U), whose
 // b_r is false in M.
+// An answer set M was found (and stored).  Asking for one answer set, or
+// having all asked for, ends the search; otherwise M is blocked by the
+// learned nogood {T p : p in M} (answer sets are incomparable under set
+// inclusion, so it excludes M alone) and the search restarts.
+DEV void answer_set(Ctx& c, Ctl& k, const KArgs& a) {
+    const int T = c.T, tid = c.tid, A = k.A;
+    k.models += 1;
+    if (!c.enumerate || a.max_models == 1) {
+        k.status = ST_SAT;
+        return;
+    }
+    k.hash = fnv(k.hash, 8);
+    k.hash = fnv(k.hash, (int32_t)k.models);
+    if (a.max_models > 0 && k.models >= a.max_models) {
+        k.status = ST_SAT;
+        return;
+    }
+    unsigned long long cnt = 0ull;
+    for (int p = 1 + tid; p <= A; p += T) cnt += vget(c.valb, p) == VT ? 1ull : 0ull;
+    const int nN = (int)block_sum_u64(c, cnt);
+    if (k.n_learned + 1 > a.cap_ng || k.learned_lits + nN > a.cap_lits) {
+        k.status = ST_UNKNOWN;
+        bar();
+        return;
+    }
+    // the true atoms, ascending: a block scan per chunk of T atoms
+    const int base = uni(c.loff[k.n_learned]);
+    int done = 0;
+    for (int b0 = 1; b0 <= A; b0 += T) {
+        const int p = b0 + tid;
+        const int f = (p <= A && vget(c.valb, p) == VT) ? 1 : 0;
+        const int inc = wave_incl_scan(f, c.lane);
+        c.scr->wsum[c.wid] = __shfl(inc, 63, 64);   // identical from the wave's lanes
+        bar();
+        int off = 0, tot = 0;
+        for (int w = 0; w < c.nw; ++w) {
+            const int x = c.scr->wsum[w];
+            off += w < c.wid ? x : 0;
+            tot += x;
+        }
+        if (f) c.llits[base + done + off + inc - 1] = p;
+        done += uni(tot);
+        bar();
+    }
+    const int newid = k.nS + k.n_learned;
+    c.loff[k.n_learned + 1] = base + nN;
+    c.scr->pool_top = k.pool_top;
+    c.scr->cap_err = 0;
+    bar();
+    add_occurrences(c, base, nN, newid);
+    bar();
+    k.pool_top = uni(c.scr->pool_top);
+    if (uni(c.scr->cap_err)) {
+        k.status = ST_E_CAPACITY;
+        bar();
+        return;
+    }
+    k.n_learned += 1;
+    k.learned_lits += nN;
+    restart(c, k);
+}
+
 DEV void step_gate(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model) {
     const int T = c.T, tid = c.tid, W = c.W, A = k.A, Rh = k.Rh;
     at_fixpoint(k);
@@ -1397,8 +1528,11 @@ DEV void step_gate(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model) {
     }
     u = block_min_i32(c, u);
     if (u == 0x7fffffff) {
-        for (int p = 1 + tid; p <= A; p += T)
-            model[p - 1] = vget(c.valb, p) == VT ? (uint8_t)1 : (uint8_t)0;
+        if (k.models < a.model_store) {
+            uint8_t* out = model + (size_t)k.models * (size_t)A;
+            for (int p = 1 + tid; p <= A; p += T)
+                out[p - 1] = vget(c.valb, p) == VT ? (uint8_t)1 : (uint8_t)0;
+        }
     } else {
         for (int w = tid; w < W; w += T)
             c.sB[w] = a.gate_mode == 1 ? alldec_word(w, k.cdl, W) : c.deps[(size_t)u * W + w];
@@ -1427,7 +1561,7 @@ DEV void step_gate(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model) {
     for (int i = tid; i < words; i += T) lm[i] = 0u;
     bar();
     if (u == 0x7fffffff) {
-        k.status = ST_SAT;
+        answer_set(c, k, a);
     } else {
         k.gate_fail += 1;
         k.pend_kind = 2;
@@ -1484,6 +1618,11 @@ DEV void run_search(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model, uint64_t t0)
         else k.t_decide += dt;
         k.steps += 1;
         k.last_step = kind;
+        if ((k.status == ST_UNSAT || k.status == ST_UNKNOWN) && k.models > 0) {
+            // the search ended after answer sets were found
+            k.exhausted = k.status == ST_UNSAT ? 1 : 0;
+            k.status = ST_SAT;
+        }
         if (k.status == ST_SAT) k.hash = fnv(k.hash, 4);
         else if (k.status == ST_UNSAT) k.hash = fnv(k.hash, 5);
         else if (k.status == ST_UNKNOWN) k.hash = fnv(k.hash, 6);
@@ -1512,15 +1651,19 @@ DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a, uint64_t t0) {
     d.hash = k.hash;
     d.status = k.status;
     d.last_step = k.last_step;
+    d.models = k.models;
+    d.restarts = k.restarts;
+    d.exhausted = k.exhausted;
     a.verdicts[k.inst] = k.status;
     bar();
 }
 
 // Three waves per SIMD: the register budget (168 VGPRs) at which the
 // search keeps six 128-thread workgroups resident per CU.  The Learning
-// step is a compile-time parameter: the Fwd-learning kernel carries none
-// of Res-learning's code or registers.
-template <int MAXT, int LR>
+// step and the enumeration of several answer sets (with restarts) are
+// compile-time parameters: the plain Fwd-learning search carries none of
+// the others' code or registers.
+template <int MAXT, int LR, int EN>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void k_search(KArgs a) {
     HIP_DYNAMIC_SHARED(unsigned long long, smem64);  // 8-byte aligned base
     __shared__ Scr scr;
@@ -1530,6 +1673,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void 
     c.decision = a.decision;
     c.fallback_after = a.fallback_after;
     c.learning = LR;
+    c.enumerate = EN;
     c.T = MAXT;
     c.tid = threadIdx.x;
     c.lane = threadIdx.x & 63;
@@ -1596,59 +1740,62 @@ size_t lds_bytes(int threads, int words) {
            sizeof(unsigned long long) * ((size_t)kFrontCap + (size_t)threads);
 }
 
-template <int LR>
-static const void* search_fn_lr(int threads) {
+template <int LR, int EN>
+static hipError_t launch_v(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {
     switch (threads) {
-    case 64: return (const void*)k_search<64, LR>;
-    case 128: return (const void*)k_search<128, LR>;
-    case 256: return (const void*)k_search<256, LR>;
-    case 512: return (const void*)k_search<512, LR>;
-    case 1024: return (const void*)k_search<1024, LR>;
-    default: return nullptr;
-    }
-}
-
-static const void* search_fn(int threads, int learning) {
-    switch (learning) {
-    case LEARN_FWD: return search_fn_lr<LEARN_FWD>(threads);
-    case LEARN_RES: return search_fn_lr<LEARN_RES>(threads);
-    default: return nullptr;
-    }
-}
-
-template <int LR>
-static hipError_t launch_lr(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {
-    switch (threads) {
-    case 64: hipLaunchKernelGGL((k_search<64, LR>), dim3(grid), dim3(64), lds, s, a); break;
-    case 128: hipLaunchKernelGGL((k_search<128, LR>), dim3(grid), dim3(128), lds, s, a); break;
-    case 256: hipLaunchKernelGGL((k_search<256, LR>), dim3(grid), dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_search<512, LR>), dim3(grid), dim3(512), lds, s, a); break;
-    case 1024: hipLaunchKernelGGL((k_search<1024, LR>), dim3(grid), dim3(1024), lds, s, a); break;
+    case 64: hipLaunchKernelGGL((k_search<64, LR, EN>), dim3(grid), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((k_search<128, LR, EN>), dim3(grid), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_search<256, LR, EN>), dim3(grid), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_search<512, LR, EN>), dim3(grid), dim3(512), lds, s, a); break;
+    case 1024: hipLaunchKernelGGL((k_search<1024, LR, EN>), dim3(grid), dim3(1024), lds, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+static int enumerates(const KArgs& a) { return a.max_models != 1 || a.restart_every != 0; }
+
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {
-    switch (a.learning) {
-    case LEARN_FWD: return launch_lr<LEARN_FWD>(a, threads, grid, lds, s);
-    case LEARN_RES: return launch_lr<LEARN_RES>(a, threads, grid, lds, s);
-    default: return hipErrorInvalidValue;
+    const int en = enumerates(a);
+    if (a.learning == LEARN_FWD) return en ? launch_v<LEARN_FWD, 1>(a, threads, grid, lds, s)
+                                           : launch_v<LEARN_FWD, 0>(a, threads, grid, lds, s);
+    if (a.learning == LEARN_RES) return en ? launch_v<LEARN_RES, 1>(a, threads, grid, lds, s)
+                                           : launch_v<LEARN_RES, 0>(a, threads, grid, lds, s);
+    return hipErrorInvalidValue;
+}
+
+template <int LR, int EN>
+static const void* search_fn_v(int threads) {
+    switch (threads) {
+    case 64: return (const void*)k_search<64, LR, EN>;
+    case 128: return (const void*)k_search<128, LR, EN>;
+    case 256: return (const void*)k_search<256, LR, EN>;
+    case 512: return (const void*)k_search<512, LR, EN>;
+    case 1024: return (const void*)k_search<1024, LR, EN>;
+    default: return nullptr;
     }
+}
+
+static const void* search_fn(int threads, int learning, int en) {
+    if (learning == LEARN_FWD) return en ? search_fn_v<LEARN_FWD, 1>(threads) : search_fn_v<LEARN_FWD, 0>(threads);
+    if (learning == LEARN_RES) return en ? search_fn_v<LEARN_RES, 1>(threads) : search_fn_v<LEARN_RES, 0>(threads);
+    return nullptr;
 }
 
 hipError_t set_max_lds(int threads, size_t lds) {
-    for (int lr : {(int)LEARN_FWD, (int)LEARN_RES}) {
-        const void* f = search_fn(threads, lr);
-        if (!f) return hipErrorInvalidValue;
-        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    for (int lr : {(int)LEARN_FWD, (int)LEARN_RES})
+        for (int en = 0; en < 2; ++en) {
+            const void* f = search_fn(threads, lr, en);
+            if (!f) return hipErrorInvalidValue;
+            const hipError_t e =
+                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
     return hipSuccess;
 }
 
-hipError_t occupancy(int threads, int learning, size_t lds, int* blocks_per_cu) {
-    const void* f = search_fn(threads, learning);
+hipError_t occupancy(int threads, int learning, int en, size_t lds, int* blocks_per_cu) {
+    const void* f = search_fn(threads, learning, en);
     if (!f) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, lds);
 }

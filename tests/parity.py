@@ -6,7 +6,8 @@ import numpy as np
 import oracle
 
 STAT_KEYS = ("rounds", "visits", "literal_checks", "propagations", "decisions", "conflicts",
-             "learned", "learned_len", "gate_failures", "completes", "trace_hash")
+             "learned", "learned_len", "gate_failures", "completes", "models", "restarts",
+             "trace_hash")
 
 # oracle status -> library status
 STATUS = {oracle.RUNNING: 6, oracle.SAT: 1, oracle.UNSAT: 2, oracle.UNKNOWN: 3,

@@ -27,6 +27,7 @@ E_INVALID, E_INTERNAL = -1, -5
 ST_NONE, ST_INIT, ST_ROUND, ST_LEARN, ST_DECIDE, ST_COMPLETE, ST_GATE, ST_DONE = range(8)
 GATE_UNFOUNDED, GATE_ALLDEC = 0, 1
 LEARN_FWD, LEARN_RES = 0, 1
+DEC_OCC, DEC_SCORE, DEC_JW, DEC_ACTIVITY = 0, 1, 2, 3
 STEP_NAMES = {ST_INIT: "init", ST_ROUND: "round", ST_LEARN: "learn", ST_DECIDE: "decide",
               ST_COMPLETE: "complete", ST_GATE: "gate", ST_DONE: "done"}
 
@@ -96,7 +97,10 @@ def lib():
         L.or_solve.argtypes = [C.c_int32, C.c_int32, i32p, i64p, i32p, C.c_int32, C.c_int32,
                                C.POINTER(Limits), np.ctypeslib.ndpointer(np.uint8, flags="C"),
                                C.POINTER(Stats), C.c_void_p, C.c_int32, C.c_int32, C.c_int64,
-                               C.c_int64]
+                               C.c_int64, C.c_int32]
+        L.or_set_decision.argtypes = [P, C.c_int32]
+        L.or_set_decision.restype = C.c_int32
+        L.or_atom_scores.argtypes = [P, C.c_int32, i32p]
         L.or_set_enum.argtypes = [P, C.c_int64, C.c_int64]
         L.or_set_enum.restype = C.c_int32
         L.or_models.argtypes = [P, np.ctypeslib.ndpointer(np.uint8, flags="C"), C.c_int64]
@@ -141,7 +145,7 @@ class Solver:
     """One program in the oracle, steppable."""
 
     def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED, learning: int = LEARN_FWD,
-                 max_models: int = 1, restart_every: int = 0):
+                 max_models: int = 1, restart_every: int = 0, decision: int = DEC_OCC):
         L = lib()
         err = C.c_int32(0)
         self._h = L.or_create(int(prog.n_atoms), int(prog.n_rules),
@@ -156,6 +160,8 @@ class Solver:
             raise ValueError("unknown learning mode")
         if L.or_set_enum(self._h, int(max_models), int(restart_every)) != 0:
             raise ValueError("max_models and restart_every must be >= 0")
+        if L.or_set_decision(self._h, int(decision)) != 0:
+            raise ValueError("decision must be DEC_OCC, DEC_JW or DEC_ACTIVITY")
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -223,6 +229,14 @@ class Solver:
         lib().or_nogoods(self._h, off, lits)
         return off, lits[:nl]
 
+    def atom_scores(self, kind: int) -> np.ndarray:
+        """Per-atom scores (index 0 unused): 0 occurrences, 1 Jeroslow-Wang
+        (fixed point), 2 the current activity."""
+        A = int(self.dims()[1])
+        o = np.zeros(A + 1, np.int32)
+        lib().or_atom_scores(self._h, int(kind), o)
+        return o
+
     def occ(self) -> np.ndarray:
         A = int(self.dims()[1])
         o = np.zeros(A + 1, np.int32)
@@ -246,7 +260,7 @@ class Solver:
 
 def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = None,
           scores=None, fallback_after: int = 10, learning: int = LEARN_FWD,
-          max_models: int = 1, restart_every: int = 0):
+          max_models: int = 1, restart_every: int = 0, decision: int = DEC_OCC):
     """Encode and solve in one call; returns (status, model or None, stats).
     ``scores`` (int32[n_atoms + 1]) selects the score-driven Decision; the
     model is the first answer set found."""
@@ -264,16 +278,16 @@ def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = 
                     np.ascontiguousarray(prog.body_lits, np.int32), int(W), int(gate),
                     C.byref(limits) if limits else None, m, C.byref(st),
                     sc.ctypes.data if sc is not None else None, int(fallback_after),
-                    int(learning), int(max_models), int(restart_every))
+                    int(learning), int(max_models), int(restart_every), int(decision))
     return rc, (m[:A].copy() if rc == SAT else None), st.as_dict()
 
 
 def enumerate_models(prog, max_models: int = 0, restart_every: int = 0, W: int = 1,
                      gate: int = GATE_UNFOUNDED, learning: int = LEARN_FWD,
-                     limits: Limits | None = None):
+                     limits: Limits | None = None, decision: int = DEC_OCC):
     """Run the search for up to ``max_models`` answer sets (0: all); returns
     (status, list of answer sets in the order found, stats, exhausted)."""
     s = Solver(prog, W=W, gate=gate, learning=learning, max_models=max_models,
-               restart_every=restart_every)
+               restart_every=restart_every, decision=decision)
     rc = s.run(limits)
     return rc, s.models(), s.stats(), s.exhausted()

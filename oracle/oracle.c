@@ -68,6 +68,13 @@
  *     with no reason at the conflict level (a CompleteAssignment literal), and
  *     every stability-gate conflict, is learned by Fwd-learning instead; a
  *     round conflict with no literal above level 1 means UNSAT;
+ *   - the Decision's score may also be the Jeroslow-Wang score of the head
+ *     over the static nogoods, J(p) = sum over nogoods holding a literal of
+ *     p of 2^-|delta|, in fixed point: sum of 2^(16-|delta|), nothing for
+ *     |delta| > 16; or the activity of the head: it starts at the occurrence
+ *     count, every literal of a nogood learned from a conflict adds 8 to its
+ *     atom (an auxiliary variable of rule r counts for the head of r), and
+ *     after every 64th such nogood all activities are halved;
  *   - supplied scores fall back to the occurrence heuristic, for the rest of
  *     the search, once `fallback_after` conflicts come in a row: the count
  *     grows at every conflict and restarts from zero whenever a decision's
@@ -83,6 +90,7 @@ enum { ST_NONE = 0, ST_INIT = 1, ST_ROUND = 2, ST_LEARN = 3, ST_DECIDE = 4,
        ST_COMPLETE = 5, ST_GATE = 6, ST_DONE = 7 };
 enum { GATE_UNFOUNDED = 0, GATE_ALLDEC = 1 };
 enum { LEARN_FWD = 0, LEARN_RES = 1 };
+enum { DEC_OCC = 0, DEC_SCORE = 1, DEC_JW = 2, DEC_ACTIVITY = 3 };
 
 typedef struct {
     int64_t rounds, visits, literal_checks, propagations, decisions, conflicts,
@@ -120,6 +128,9 @@ typedef struct {
     ivec ng_lits;
     ivec *map;                 /* [2(V+1)] literal -> nogood ids ascending */
     int32_t *occ;              /* [A+1] static occurrence count */
+    int32_t *jw;               /* [A+1] static Jeroslow-Wang score (fixed point) */
+    int32_t *act;              /* [A+1] activity */
+    int32_t decision;          /* DEC_OCC, DEC_JW or DEC_ACTIVITY when no scores drive it */
     int32_t *score;            /* [A+1] supplied decision scores, or NULL */
     int32_t use_score;         /* 1 while the supplied scores drive Decision */
     int32_t fallback_after;    /* <0: never fall back */
@@ -344,13 +355,20 @@ static int encode(or_solver *s, int32_t n_atoms, int32_t n_rules,
     s->lits0 = s->ng_lits.n;
 
     s->occ = (int32_t *)calloc((size_t)A + 1, sizeof(int32_t));
+    s->jw = (int32_t *)calloc((size_t)A + 1, sizeof(int32_t));
+    s->act = (int32_t *)calloc((size_t)A + 1, sizeof(int32_t));
     for (int64_t g = 0; g < G; ++g) {
         /* the atoms of a nogood are distinct, so each counts once per nogood */
+        int32_t len = s->ng_off.a[g + 1] - s->ng_off.a[g];
         for (int32_t k = s->ng_off.a[g]; k < s->ng_off.a[g + 1]; ++k) {
             int32_t v = var_of(s->ng_lits.a[k]);
-            if (v <= A) s->occ[v] += 1;
+            if (v <= A) {
+                s->occ[v] += 1;
+                if (len <= 16) s->jw[v] += 1 << (16 - len);
+            }
         }
     }
+    for (int32_t p = 0; p <= A; ++p) s->act[p] = s->occ[p];
     free(goff.a); free(glits.a); free(tmp.a);
     free(cpos_off); free(cneg_off); free(cpos); free(cneg);
     return 0;
@@ -409,7 +427,7 @@ void or_free(void *h) {
     free(s->ng_off.a); free(s->ng_lits.a);
     if (s->map)
         for (size_t i = 0; i < 2 * ((size_t)s->V + 1); ++i) free(s->map[i].a);
-    free(s->map); free(s->occ); free(s->score);
+    free(s->map); free(s->occ); free(s->jw); free(s->act); free(s->score);
     free(s->val); free(s->lvl); free(s->deps); free(s->tmpdeps); free(s->pend_B);
     free(s->dec); free(s->frontier.a); free(s->win); free(s->winsign); free(s->touched);
     free(s->inM); free(s->inLM);
@@ -725,6 +743,17 @@ static void step_learn(or_solver *s, const or_limits *lim) {
     s->learned_lits += nN;
     s->st.learned += 1;
     s->st.learned_len += nN;
+    if (s->decision == DEC_ACTIVITY) {
+        /* activity: every literal bumps its atom (an auxiliary variable of
+         * rule r stands for the head of r); halve all every 64 nogoods */
+        for (int64_t i = 0; i < nN; ++i) {
+            int32_t v = var_of(N[i]);
+            int32_t p = v <= s->A ? v : s->rhead[(v - s->A - 1) / 3];
+            s->act[p] += 8;
+        }
+        if (s->st.learned % 64 == 0)
+            for (int32_t p = 0; p <= s->A; ++p) s->act[p] >>= 1;
+    }
     fnv(s, 2); fnv(s, s->pend_kind == 1 ? s->pend_id : -1); fnv(s, (int32_t)nN); fnv(s, bj);
     s->since_restart += 1;
     if (s->restart_every > 0 && s->since_restart >= s->restart_every) {
@@ -764,7 +793,9 @@ static void step_learn(or_solver *s, const or_limits *lim) {
 /* S8: pick an applicable rule (T t_r in A, F n_r not in A, head unassigned)
  * by the highest score of its head, ties to the lowest rule. */
 static int32_t find_decision(const or_solver *s) {
-    const int32_t *sc = s->use_score ? s->score : s->occ;
+    const int32_t *sc = s->use_score ? s->score
+                      : s->decision == DEC_JW ? s->jw
+                      : s->decision == DEC_ACTIVITY ? s->act : s->occ;
     int32_t best = -1;
     int64_t bestkey = INT64_MIN;
     for (int32_t j = 0; j < s->Rh; ++j) {
@@ -991,6 +1022,24 @@ int32_t or_set_scores(void *h, const int32_t *score, int32_t fallback_after) {
     return 0;
 }
 
+/* Choose the Decision score when no per-atom scores are supplied (DEC_OCC,
+ * DEC_JW, DEC_ACTIVITY) before the first step.  Returns 0, or OR_E_INVALID. */
+int32_t or_set_decision(void *h, int32_t mode) {
+    or_solver *s = (or_solver *)h;
+    if (s->last_step != ST_NONE || (mode != DEC_OCC && mode != DEC_JW && mode != DEC_ACTIVITY))
+        return OR_E_INVALID;
+    s->decision = mode;
+    return 0;
+}
+
+/* static scores of atoms 0..A: kind 0 occurrences, 1 Jeroslow-Wang,
+ * 2 current activity */
+void or_atom_scores(void *h, int32_t kind, int32_t *out) {
+    or_solver *s = (or_solver *)h;
+    const int32_t *src = kind == 1 ? s->jw : kind == 2 ? s->act : s->occ;
+    memcpy(out, src, sizeof(int32_t) * ((size_t)s->A + 1));
+}
+
 /* Choose the Learning step (LEARN_FWD, LEARN_RES) before the first step.
  * Returns 0, or OR_E_INVALID. */
 int32_t or_set_learning(void *h, int32_t mode) {
@@ -1064,12 +1113,14 @@ int32_t or_solve(int32_t n_atoms, int32_t n_rules, const int32_t *head,
                  const int64_t *body_off, const int32_t *body_lits, int32_t W,
                  int32_t gate_mode, const or_limits *lim, uint8_t *model,
                  or_stats *st, const int32_t *score, int32_t fallback_after,
-                 int32_t learning, int64_t max_models, int64_t restart_every) {
+                 int32_t learning, int64_t max_models, int64_t restart_every,
+                 int32_t decision) {
     int32_t err = 0;
     void *h = or_create(n_atoms, n_rules, head, body_off, body_lits, W, gate_mode, &err);
     if (!h) return err;
     if (score) or_set_scores(h, score, fallback_after);
-    if (or_set_learning(h, learning) != 0 || or_set_enum(h, max_models, restart_every) != 0) {
+    if (or_set_learning(h, learning) != 0 || or_set_enum(h, max_models, restart_every) != 0 ||
+        (!score && or_set_decision(h, decision) != 0)) {
         or_free(h);
         return OR_E_INVALID;
     }

@@ -258,6 +258,8 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=2)
     ap.add_argument("--no-res", action="store_true", help="skip the Res-learning leg")
     ap.add_argument("--no-enum", action="store_true", help="skip the several-answer-sets leg")
+    ap.add_argument("--no-heur", action="store_true",
+                    help="skip the Jeroslow-Wang and activity Decision legs")
     ap.add_argument("--enum-models", type=int, default=16, help="answer sets asked per program")
     ap.add_argument("--res-steps", type=int, default=2)
     ap.add_argument("--graph-steps", type=int, default=2,
@@ -403,6 +405,9 @@ def main():
     if not args.no_res:
         log("[bench] Res-learning leg")
         line["res"] = res_leg(args, P, progs, verd, stream, dev, lim, ms_step, cth)
+    if not args.no_heur:
+        log("[bench] Jeroslow-Wang and activity Decision legs")
+        line["heuristics"] = heur_leg(args, P, progs, verd, stream, dev, lim, ms_step, cth)
     if not args.no_enum:
         log("[bench] several-answer-sets leg")
         line["enum"] = enum_leg(args, P, progs, verd, stream, dev, lim, cth)
@@ -448,6 +453,40 @@ def res_leg(args, P, progs, fwd_verd, stream, dev, lim, fwd_ms_step, cth):
     }
     del batch
     torch.cuda.empty_cache()
+    return out
+
+
+def heur_leg(args, P, progs, plain_verd, stream, dev, lim, plain_ms_step, cth):
+    """The same batch, budget and schedule with the Jeroslow-Wang and the
+    activity Decision scores in place of occurrence counts."""
+    import torch
+    plain_ips = int(((plain_verd == 1) | (plain_verd == 2)).sum()) / (plain_ms_step / 1000.0)
+    out = {}
+    for name, dec in (("jw", P.DECISION_JW), ("activity", P.DECISION_ACTIVITY)):
+        gp = load_programs(progs, args.W, args.cap_ng, args.cap_lits, decision=dec)
+        batch = P.Batch(gp, threads=args.threads, classes=args.classes, class_threads=cth)
+        with torch.cuda.stream(stream):
+            batch.bind(dev, stream=stream)
+        torch.cuda.synchronize()
+        ms, walls = timed_steps(batch, lim, 1, 1)
+        verd, models, stats = batch.results()
+        ms_step = float(np.sum(walls)) * 1000.0 / len(walls)
+        n_sat, n_unsat = int((verd == 1).sum()), int((verd == 2).sum())
+        n_sat_checked, bad = verify_models(progs, verd, models)
+        ips = (n_sat + n_unsat) / (ms_step / 1000.0)
+        out[name] = {
+            "ms_per_step": ms_step, "instances_per_s": ips,
+            "vs_occurrence_instances_per_s": ips / plain_ips if plain_ips > 0 else None,
+            "verdicts": {"sat": n_sat, "unsat": n_unsat, "unknown": int((verd == 3).sum()),
+                         "error": int((verd < 0).sum())},
+            "verdict_contradictions_vs_occurrence": int(
+                ((verd == 1) & (plain_verd == 2)).sum() + ((verd == 2) & (plain_verd == 1)).sum()),
+            "models_verified": {"sat": n_sat_checked, "not_stable": len(bad)},
+            "literal_checks_per_s": sum(int(s["literal_checks"]) for s in stats) / (ms_step / 1000.0),
+            "counters": search_counters(stats, ms_step),
+        }
+        del batch
+        torch.cuda.empty_cache()
     return out
 
 

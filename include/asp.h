@@ -80,6 +80,16 @@ extern "C" {
 #define ASP_DECISION_SCORE 1  /* per-atom integer scores set on the device
                                  (asp_set_scores, or the learned scorer of
                                  asp_score_program / asp_score_batch) */
+#define ASP_DECISION_JW    2  /* Jeroslow-Wang score of the head over Delta_0,
+                                 sum of 2^(16-|delta|) over the nogoods
+                                 holding a literal of it (none beyond 16
+                                 literals) */
+#define ASP_DECISION_ACTIVITY 3  /* activity of the head: starts at its
+                                 occurrence count; every literal of a nogood
+                                 learned from a conflict adds 8 to its atom
+                                 (an auxiliary variable of rule r counts for
+                                 the head of r); all halved after every 64th
+                                 such nogood */
 
 typedef struct asp_program asp_program;
 typedef struct asp_batch asp_batch;
@@ -94,7 +104,7 @@ typedef struct {
     int64_t learned_cap_ng;    /* learned nogoods kept per instance; exceeding
                                   it ends the search with ASP_UNKNOWN */
     int64_t learned_cap_lits;  /* learned literals kept per instance; idem */
-    int32_t decision;          /* ASP_DECISION_OCC or ASP_DECISION_SCORE */
+    int32_t decision;          /* ASP_DECISION_OCC, _SCORE, _JW or _ACTIVITY */
     int32_t fallback_after;    /* ASP_DECISION_SCORE: after this many
                                   conflicts in a row (the count restarts when a
                                   decision's propagation ends at a

@@ -6,4 +6,5 @@ ASP-solving", as hand-written HIP behind a C ABI (include/asp.h).
 """
 from .binding import (Batch, Program, AspError, limits, options, lib,  # noqa: F401
                       scorer_weights, SAT, UNSAT, UNKNOWN, FIXPOINT, CONFLICT, RUNNING,
-                      DECISION_OCC, DECISION_SCORE, LEARN_FWD, LEARN_RES)
+                      DECISION_OCC, DECISION_SCORE, DECISION_JW,
+                      DECISION_ACTIVITY, LEARN_FWD, LEARN_RES)

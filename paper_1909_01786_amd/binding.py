@@ -19,7 +19,7 @@ OK, SAT, UNSAT, UNKNOWN, FIXPOINT, CONFLICT, RUNNING = 0, 1, 2, 3, 4, 5, 6
 E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_INTERNAL, E_TIMEOUT = -1, -2, -3, -4, -5, -6
 STEP_NONE, STEP_INIT, STEP_ROUND, STEP_LEARN, STEP_DECIDE, STEP_COMPLETE, STEP_GATE, STEP_DONE = range(8)
 GATE_UNFOUNDED, GATE_ALLDEC = 0, 1
-DECISION_OCC, DECISION_SCORE = 0, 1
+DECISION_OCC, DECISION_SCORE, DECISION_JW, DECISION_ACTIVITY = 0, 1, 2, 3
 LEARN_FWD, LEARN_RES = 0, 1
 SCORER_F, SCORER_H, SCORER_L = 8, 64, 3
 

@@ -314,7 +314,11 @@ int32_t upload_static(const std::vector<const HostProgram*>& progs, const Plan& 
     std::vector<int32_t> mo = concat(progs, &HostProgram::map_off);
     std::vector<MapEntry> mi = concat(progs, &HostProgram::map_ent);
     std::vector<int32_t> rh = concat(progs, &HostProgram::rule_head);
-    std::vector<int32_t> ro = concat(progs, &HostProgram::rule_occ);
+    // the static per-rule score: the head's Jeroslow-Wang score, or its
+    // occurrence count (also the start of the activity and the learned
+    // Decision's fallback)
+    std::vector<int32_t> ro = concat(progs, P.decision == ASP_DECISION_JW ? &HostProgram::rule_jw
+                                                                           : &HostProgram::rule_occ);
     std::vector<int32_t> rbo = concat(progs, &HostProgram::rb_off);
     std::vector<int32_t> rbl = concat(progs, &HostProgram::rb_lits);
     HIPCHK(put(P.off_desc, P.desc.data(), sizeof(InstDesc) * P.desc.size()));
@@ -689,7 +693,8 @@ int32_t asp_load_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
     if (o.learned_cap_ng < 1 || o.learned_cap_lits < 1 || o.learned_cap_ng > (1 << 29) ||
         o.learned_cap_lits > ((int64_t)1 << 29))
         return fail(ASP_E_INVALID, "learned capacities must be in 1..2^29");
-    if (o.decision != ASP_DECISION_OCC && o.decision != ASP_DECISION_SCORE)
+    if (o.decision != ASP_DECISION_OCC && o.decision != ASP_DECISION_SCORE &&
+        o.decision != ASP_DECISION_JW && o.decision != ASP_DECISION_ACTIVITY)
         return fail(ASP_E_INVALID, "unknown decision heuristic");
     if (o.learning != ASP_LEARN_FWD && o.learning != ASP_LEARN_RES)
         return fail(ASP_E_INVALID, "unknown learning step");

@@ -194,19 +194,27 @@ int encode_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
         }
     }
 
-    // occurrence count of each atom over Delta_0 (an atom occurs at most
+    // occurrence count and Jeroslow-Wang score (sum of 2^(16-|delta|), none
+    // beyond 16 literals) of each atom over Delta_0 (an atom occurs at most
     // once per nogood), read per headed rule through its head
-    std::vector<int32_t> occ(A + 1, 0);
-    for (int32_t l : P->ng_lits) {
-        int32_t v = l < 0 ? -l : l;
-        if (v <= A) occ[v] += 1;
+    std::vector<int32_t> occ(A + 1, 0), jw(A + 1, 0);
+    for (size_t g = 0; g + 1 < P->ng_off.size(); ++g) {
+        const int32_t len = P->ng_off[g + 1] - P->ng_off[g];
+        for (int32_t q = P->ng_off[g]; q < P->ng_off[g + 1]; ++q) {
+            int32_t v = P->ng_lits[q] < 0 ? -P->ng_lits[q] : P->ng_lits[q];
+            if (v > A) continue;
+            occ[v] += 1;
+            if (len <= 16) jw[v] += 1 << (16 - len);
+        }
     }
     P->rule_head.assign(hh.begin(), hh.end());
     P->rule_occ.resize(Rh);
+    P->rule_jw.resize(Rh);
     P->rb_off.assign(Rh + 1, 0);
     P->rb_lits.clear();
     for (int64_t j = 0; j < Rh; ++j) {
         P->rule_occ[j] = occ[hh[j]];
+        P->rule_jw[j] = jw[hh[j]];
         for (int32_t p : hb[j].pos) P->rb_lits.push_back(p);
         for (int32_t q : hb[j].neg) P->rb_lits.push_back(-q);
         P->rb_off[j + 1] = (int32_t)P->rb_lits.size();

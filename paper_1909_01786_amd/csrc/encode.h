@@ -20,6 +20,7 @@ struct HostProgram {
     std::vector<MapEntry> map_ent;       // literal -> nogood entries, ids ascending
     std::vector<int32_t> rule_head;      // per headed rule
     std::vector<int32_t> rule_occ;       // occurrence count of the head in Delta_0
+    std::vector<int32_t> rule_jw;        // Jeroslow-Wang score of the head (fixed point)
     std::vector<int32_t> rb_off;         // per headed rule body (deduplicated)
     std::vector<int32_t> rb_lits;
     int64_t n_nogoods() const { return (int64_t)ng_off.size() - 1; }

@@ -84,6 +84,7 @@ struct SlotLayout {
     int64_t reason;     // int32[V+1] nogood that implied the assignment, -1 none
     int64_t mark;       // int32[V+1] resolution membership (epoch)
     int64_t resd;       // int32[V+1] variables of the nogood being resolved
+    int64_t act;        // int32[V+1] activity of each atom (activity Decision)
     int64_t stride;     // bytes of the slot
     int64_t pool_cap;   // entries
 };
@@ -119,6 +120,7 @@ __host__ __device__ inline SlotLayout slot_layout(int64_t V, int64_t Rh, int32_t
     ASP_TAKE(reason, 4 * V1);
     ASP_TAKE(mark, 4 * V1);
     ASP_TAKE(resd, 4 * V1);
+    ASP_TAKE(act, 4 * V1);
 #undef ASP_TAKE
     L.stride = o;
     return L;
@@ -139,7 +141,9 @@ enum StepKind : int32_t {
     STEP_COMPLETE = 5, STEP_GATE = 6, STEP_DONE = 7
 };
 
-enum Decision : int32_t { DECISION_OCC = 0, DECISION_SCORE = 1 };
+enum Decision : int32_t {
+    DECISION_OCC = 0, DECISION_SCORE = 1, DECISION_JW = 2, DECISION_ACTIVITY = 3
+};
 enum Learning : int32_t { LEARN_FWD = 0, LEARN_RES = 1 };
 
 enum Mode : int32_t {
@@ -175,7 +179,7 @@ struct KArgs {
     DevStats* stats;
     uint8_t* models;
     int32_t W, gate_mode;
-    int32_t decision;            // DECISION_OCC or DECISION_SCORE
+    int32_t decision;            // DECISION_OCC, _SCORE, _JW or _ACTIVITY
     int32_t fallback_after;      // conflicts in a row before scores give way; <0 never
     int32_t learning;            // LEARN_FWD or LEARN_RES
     int32_t pad1;

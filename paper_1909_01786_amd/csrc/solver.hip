@@ -90,6 +90,7 @@ struct Ctx {
     int8_t* val8;
     int32_t *lvl, *trail, *tlim, *dec, *lptr, *ln, *lcap, *loff, *llits, *pool;
     int32_t *gpos, *reason, *mark, *resd;
+    int32_t* act;           // activity of each atom (activity Decision)
     unsigned long long* win;
     uint64_t* deps;
     int64_t pool_cap;
@@ -114,7 +115,8 @@ struct Ctx {
     Scr* scr;
     int32_t W, T, tid, lane, wid, nw;
     int32_t decision, fallback_after, learning;
-    int32_t enumerate;      // several answer sets or restarts (compile-time in k_search)
+    int32_t ext;            // extended search: several answer sets, restarts, activity
+                            // (compile-time in k_search)
     unsigned long long my_visits, my_checks;
 };
 
@@ -348,6 +350,7 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     c.reason = (int32_t*)(slot + lay.reason);
     c.mark = (int32_t*)(slot + lay.mark);
     c.resd = (int32_t*)(slot + lay.resd);
+    c.act = (int32_t*)(slot + lay.act);
     c.pool_cap = lay.pool_cap;
 }
 
@@ -372,6 +375,9 @@ DEV void reset_search(Ctx& c, Ctl& k) {
         c.lptr[q] = 0;
     }
     for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
+    // activities start at the heads' occurrence counts (the static table)
+    if (c.ext && c.decision == DECISION_ACTIVITY)
+        for (int j = tid; j < k.Rh; j += T) c.act[c.RH[j]] = c.RO[j];
     c.loff[0] = 0;
     k.cdl = 1;
     k.qh = k.qt = 0;
@@ -678,7 +684,7 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
                 s0 = c.MO[li];
                 cs = c.MO[li + 1] - s0;
             }
-            const bool dec_lit = c.learning == LEARN_RES || (c.enumerate && code == VT) ||
+            const bool dec_lit = c.learning == LEARN_RES || (c.ext && code == VT) ||
                                  (code == VT && x > k.A && (x - k.A - 1) % 3 == 0);
             const int lli = 2 * x + (code == VF ? 1 : 0);
             const int l0 = dec_lit ? c.lptr[lli] : 0;
@@ -1259,8 +1265,20 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     c.loff[k.n_learned + 1] = base + nN;
     bar();
     add_occurrences(c, base, nN, newid);
+    if (c.ext && c.decision == DECISION_ACTIVITY) {
+        // every literal bumps its atom (an auxiliary variable of rule r
+        // stands for the head of r); all are halved after every 64th nogood
+        for (int i = tid; i < nN; i += T) {
+            const int v = lvar(c.llits[base + i]);
+            atomicAdd(&c.act[v <= k.A ? v : c.RH[(v - k.A - 1) / 3]], 8);
+        }
+        if ((k.learned + 1) % 64 == 0) {
+            bar();
+            for (int p = 1 + tid; p <= k.A; p += T) c.act[p] >>= 1;
+        }
+    }
     k.since_restart += 1;
-    if (c.enumerate && a.restart_every > 0 && k.since_restart >= a.restart_every) {
+    if (c.ext && a.restart_every > 0 && k.since_restart >= a.restart_every) {
         bar();
         k.pool_top = uni(c.scr->pool_top);
         if (uni(c.scr->cap_err)) {
@@ -1337,21 +1355,26 @@ DEV void at_fixpoint(Ctl& k) {
     if (k.dec_open) k.consec = 0;
 }
 
-DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
-    const int T = c.T, tid = c.tid, W = c.W, A = k.A, Rh = k.Rh;
-    at_fixpoint(k);
-    // key: head score (signed, biased to keep its order) then lowest rule
-    const int32_t* score = k.use_score ? c.RS : c.RO;
+// This lane's best applicable rule: key (score of the head, biased to keep
+// its order as unsigned) << 32 | (~rule), 0 if none.  BY_ACT reads the
+// head's activity, else score[j]; four rules per lane at a time, so their
+// loads are issued together.
+template <bool BY_ACT>
+DEV unsigned long long best_rule(Ctx& c, const Ctl& k, const int32_t* score) {
+    const int T = c.T, A = k.A, Rh = k.Rh;
     unsigned long long best = 0ull;
-    // four rules per lane at a time: their loads are issued together
     constexpr int U = 4;
-    for (int j0 = tid; j0 < Rh; j0 += U * T) {
+    for (int j0 = c.tid; j0 < Rh; j0 += U * T) {
         int hp[U], sc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = j0 + u * T;
             hp[u] = j < Rh ? c.RH[j] : 0;
-            sc[u] = j < Rh ? score[j] : 0;
+            if (!BY_ACT) sc[u] = j < Rh ? score[j] : 0;
+        }
+        if (BY_ACT) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) sc[u] = j0 + u * T < Rh ? c.act[hp[u]] : 0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1365,6 +1388,19 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
             best = key > best ? key : best;
         }
     }
+    return best;
+}
+
+DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
+    const int T = c.T, tid = c.tid, W = c.W, A = k.A;
+    at_fixpoint(k);
+    // key: head score (signed, biased to keep its order) then lowest rule;
+    // the score is the static per-rule table (occurrences or Jeroslow-Wang),
+    // the supplied scores, or the head's activity
+    const unsigned long long mine = c.ext && c.decision == DECISION_ACTIVITY
+                                        ? best_rule<true>(c, k, c.RO)
+                                        : best_rule<false>(c, k, k.use_score ? c.RS : c.RO);
+    unsigned long long best = mine;
     best = block_max_u64(c, best);
     bar();
     if (best != 0ull) {
@@ -1437,7 +1473,7 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
 DEV void answer_set(Ctx& c, Ctl& k, const KArgs& a) {
     const int T = c.T, tid = c.tid, A = k.A;
     k.models += 1;
-    if (!c.enumerate || a.max_models == 1) {
+    if (!c.ext || a.max_models == 1) {
         k.status = ST_SAT;
         return;
     }
@@ -1660,9 +1696,9 @@ DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a, uint64_t t0) {
 
 // Three waves per SIMD: the register budget (168 VGPRs) at which the
 // search keeps six 128-thread workgroups resident per CU.  The Learning
-// step and the enumeration of several answer sets (with restarts) are
-// compile-time parameters: the plain Fwd-learning search carries none of
-// the others' code or registers.
+// step and the extended search (several answer sets, restarts, the
+// activity Decision) are compile-time parameters: the plain Fwd-learning
+// search carries none of the others' code or registers.
 template <int MAXT, int LR, int EN>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void k_search(KArgs a) {
     HIP_DYNAMIC_SHARED(unsigned long long, smem64);  // 8-byte aligned base
@@ -1673,7 +1709,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void 
     c.decision = a.decision;
     c.fallback_after = a.fallback_after;
     c.learning = LR;
-    c.enumerate = EN;
+    c.ext = EN;
     c.T = MAXT;
     c.tid = threadIdx.x;
     c.lane = threadIdx.x & 63;
@@ -1753,10 +1789,12 @@ static hipError_t launch_v(const KArgs& a, int threads, int grid, size_t lds, hi
     return hipGetLastError();
 }
 
-static int enumerates(const KArgs& a) { return a.max_models != 1 || a.restart_every != 0; }
+static int extended(const KArgs& a) {
+    return a.max_models != 1 || a.restart_every != 0 || a.decision == DECISION_ACTIVITY;
+}
 
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {
-    const int en = enumerates(a);
+    const int en = extended(a);
     if (a.learning == LEARN_FWD) return en ? launch_v<LEARN_FWD, 1>(a, threads, grid, lds, s)
                                            : launch_v<LEARN_FWD, 0>(a, threads, grid, lds, s);
     if (a.learning == LEARN_RES) return en ? launch_v<LEARN_RES, 1>(a, threads, grid, lds, s)

@@ -231,7 +231,7 @@ def search_counters(stats, ms_step):
 
 def verify_models(progs, verd, models):
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from judge import is_stable
+    from brute import is_stable
     sat = np.nonzero(verd == 1)[0]
     bad = [int(i) for i in sat if not is_stable(progs[i], models[i])]
     return int(sat.size), bad
@@ -279,7 +279,7 @@ def main():
         write_traffic(*args.write_traffic, config)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the batch would shard by instance across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
@@ -507,7 +507,7 @@ def enum_leg(args, P, progs, plain_verd, stream, dev, lim, cth):
     exhausted = np.array([int(s["exhausted"]) for s in stats])
     contra = int(((found > 0) & (plain_verd == 2)).sum() + ((found == 0) & (plain_verd == 1)).sum())
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from judge import is_stable
+    from brute import is_stable
     n_checked = bad = dup = 0
     for i in np.nonzero(found > 0)[0]:
         ms_i = models[i]

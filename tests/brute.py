@@ -1,4 +1,4 @@
-"""Answer-set judge, independent of both solvers.
+"""Brute-force answer sets, independent of both solvers.
 
 Straight from the definitions of the paper's Preliminaries:
 

@@ -14,7 +14,7 @@ import pytest
 import aspgen
 import oracle
 from oracle import mpnn
-from judge import is_stable
+from brute import is_stable
 from parity import assert_same_state, assert_same_stats, STATUS
 
 pytestmark = pytest.mark.gpu

@@ -12,7 +12,7 @@ import pytest
 
 import aspgen
 import oracle
-from judge import is_stable
+from brute import is_stable
 from parity import STATUS, assert_same_stats
 
 pytestmark = pytest.mark.gpu

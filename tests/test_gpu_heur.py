@@ -10,7 +10,7 @@ import pytest
 
 import aspgen
 import oracle
-from judge import is_stable, stable_models
+from brute import is_stable, stable_models
 from parity import assert_same_state, assert_same_stats, STATUS
 
 pytestmark = pytest.mark.gpu

@@ -11,7 +11,7 @@ import pytest
 
 import aspgen
 import oracle
-from judge import is_stable, model_to_mask, stable_models
+from brute import is_stable, model_to_mask, stable_models
 from parity import assert_same_state, assert_same_stats, to_lib_state, STATUS
 
 pytestmark = pytest.mark.gpu

@@ -16,7 +16,7 @@ import oracle
 from fullscan import (completion_extension, decision_choice, expected_round,
                       full_scan, levels_of, lit_val, lit_var, nogoods_list,
                       occurrences, satisfies)
-from judge import (completion_models, is_stable, mask_to_model, model_to_mask,
+from brute import (completion_models, is_stable, mask_to_model, model_to_mask,
                    stable_models)
 
 

@@ -15,7 +15,7 @@ import pytest
 import aspgen
 import oracle
 from oracle import mpnn
-from judge import is_stable, stable_models
+from brute import is_stable, stable_models
 
 
 # ------------------------------------------------ score-driven Decision

@@ -17,7 +17,7 @@ import pytest
 
 import aspgen
 import oracle
-from judge import is_stable, model_to_mask, stable_models
+from brute import is_stable, model_to_mask, stable_models
 
 
 def _as_set(models):

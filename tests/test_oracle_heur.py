@@ -18,7 +18,7 @@ import pytest
 import aspgen
 import oracle
 from fullscan import nogoods_list
-from judge import is_stable, stable_models
+from brute import is_stable, stable_models
 from test_oracle import norm_rules
 
 

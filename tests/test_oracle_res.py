@@ -14,7 +14,7 @@ import pytest
 import aspgen
 import oracle
 from fullscan import lit_val, lit_var, nogoods_list, completion_extension
-from judge import is_stable, stable_models
+from brute import is_stable, stable_models
 
 
 def _walk_res(prog, max_steps=4000):

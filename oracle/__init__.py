@@ -97,7 +97,9 @@ def lib():
         L.or_solve.argtypes = [C.c_int32, C.c_int32, i32p, i64p, i32p, C.c_int32, C.c_int32,
                                C.POINTER(Limits), np.ctypeslib.ndpointer(np.uint8, flags="C"),
                                C.POINTER(Stats), C.c_void_p, C.c_int32, C.c_int32, C.c_int64,
-                               C.c_int64, C.c_int32]
+                               C.c_int64, C.c_int32, C.c_int32]
+        L.or_set_learn_conflicts.argtypes = [P, C.c_int32]
+        L.or_set_learn_conflicts.restype = C.c_int32
         L.or_set_decision.argtypes = [P, C.c_int32]
         L.or_set_decision.restype = C.c_int32
         L.or_atom_scores.argtypes = [P, C.c_int32, i32p]
@@ -145,7 +147,8 @@ class Solver:
     """One program in the oracle, steppable."""
 
     def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED, learning: int = LEARN_FWD,
-                 max_models: int = 1, restart_every: int = 0, decision: int = DEC_OCC):
+                 max_models: int = 1, restart_every: int = 0, decision: int = DEC_OCC,
+                 learn_conflicts: int = 1):
         L = lib()
         err = C.c_int32(0)
         self._h = L.or_create(int(prog.n_atoms), int(prog.n_rules),
@@ -162,6 +165,8 @@ class Solver:
             raise ValueError("max_models and restart_every must be >= 0")
         if L.or_set_decision(self._h, int(decision)) != 0:
             raise ValueError("decision must be DEC_OCC, DEC_JW or DEC_ACTIVITY")
+        if L.or_set_learn_conflicts(self._h, int(learn_conflicts)) != 0:
+            raise ValueError("learn_conflicts must be in 1..8")
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -260,7 +265,8 @@ class Solver:
 
 def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = None,
           scores=None, fallback_after: int = 10, learning: int = LEARN_FWD,
-          max_models: int = 1, restart_every: int = 0, decision: int = DEC_OCC):
+          max_models: int = 1, restart_every: int = 0, decision: int = DEC_OCC,
+          learn_conflicts: int = 1):
     """Encode and solve in one call; returns (status, model or None, stats).
     ``scores`` (int32[n_atoms + 1]) selects the score-driven Decision; the
     model is the first answer set found."""
@@ -278,16 +284,19 @@ def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = 
                     np.ascontiguousarray(prog.body_lits, np.int32), int(W), int(gate),
                     C.byref(limits) if limits else None, m, C.byref(st),
                     sc.ctypes.data if sc is not None else None, int(fallback_after),
-                    int(learning), int(max_models), int(restart_every), int(decision))
+                    int(learning), int(max_models), int(restart_every), int(decision),
+                    int(learn_conflicts))
     return rc, (m[:A].copy() if rc == SAT else None), st.as_dict()
 
 
 def enumerate_models(prog, max_models: int = 0, restart_every: int = 0, W: int = 1,
                      gate: int = GATE_UNFOUNDED, learning: int = LEARN_FWD,
-                     limits: Limits | None = None, decision: int = DEC_OCC):
+                     limits: Limits | None = None, decision: int = DEC_OCC,
+                     learn_conflicts: int = 1):
     """Run the search for up to ``max_models`` answer sets (0: all); returns
     (status, list of answer sets in the order found, stats, exhausted)."""
     s = Solver(prog, W=W, gate=gate, learning=learning, max_models=max_models,
-               restart_every=restart_every, decision=decision)
+               restart_every=restart_every, decision=decision,
+               learn_conflicts=learn_conflicts)
     rc = s.run(limits)
     return rc, s.models(), s.stats(), s.exhausted()

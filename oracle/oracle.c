@@ -50,6 +50,14 @@
  *   - when the search ends UNSAT (or UNKNOWN) after at least one answer set,
  *     the verdict is SAT; after UNSAT the enumeration is exhausted.
  *
+ * Several conflicts per Learning step (the paper lets the solver select one
+ * or more of a round's conflicts, and take the lowest backjump level among
+ * the learned nogoods): with learn_conflicts = K > 1 the K shortest (then
+ * lowest-id) distinct conflicts of a round are each learned on the same
+ * assignment, in that order, with consecutive ids; the backjump goes to
+ * the lowest of their levels and the first nogood reaching it asserts its
+ * latest literal.  One of them holding at the root means no answer set.
+ *
  * Readings of the paper taken here:
  *   - levels start at 1 (root); the decision at level l >= 2 sets Deps bit
  *     min(l-1, 64W-1), so bit 64W-1 stands for every level >= 64W;
@@ -158,9 +166,12 @@ typedef struct {
     int32_t *dec;              /* [Rh+2] decision literal of each level */
     ivec frontier;
 
-    /* pending conflict: kind 0 none, 1 round (id), 2 gate (bits) */
+    /* pending conflict: kind 0 none, 1 round (ids), 2 gate (bits) */
     int32_t pend_kind;
-    int32_t pend_id;
+    int32_t pend_id;           /* the first (shortest, then lowest id) round conflict */
+    int32_t pend_ids[8];       /* the round conflicts selected for learning, ranked */
+    int32_t n_pend;
+    int32_t learn_conflicts;   /* round conflicts learned per Learning step, 1..8 */
     uint64_t *pend_B;
 
     int32_t status, last_step;
@@ -412,6 +423,7 @@ void *or_create(int32_t n_atoms, int32_t n_rules, const int32_t *head,
     s->mark = (int32_t *)calloc(V1, sizeof(int32_t));
     s->cdl = 1;
     s->max_models = 1;
+    s->learn_conflicts = 1;
     s->need_init = 1;
     s->st.trace_hash = 1469598103934665603ull;
     s->status = OR_RUNNING;
@@ -493,10 +505,28 @@ static int classify(const or_solver *s, int64_t id, int32_t *u) {
 
 /* S4: one PropagateAndCheck round (Sect. 4.1) in Jacobi form.
  * S5: among the round's conflicts, keep the shortest, ties by lowest id. */
+/* keep the K = learn_conflicts smallest distinct (length, id) conflicts */
+static void note_conflict(or_solver *s, int32_t id) {
+    const int32_t K = s->learn_conflicts;
+    int32_t n = s->n_pend;
+    for (int32_t i = 0; i < n; ++i)
+        if (s->pend_ids[i] == id) return;
+    int32_t pos = n;
+    while (pos > 0) {
+        int32_t o = s->pend_ids[pos - 1];
+        if (ng_len(s, o) < ng_len(s, id) || (ng_len(s, o) == ng_len(s, id) && o < id)) break;
+        --pos;
+    }
+    if (pos >= K) return;
+    for (int32_t i = (n < K ? n : K - 1); i > pos; --i) s->pend_ids[i] = s->pend_ids[i - 1];
+    s->pend_ids[pos] = id;
+    if (n < K) s->n_pend = n + 1;
+}
+
 static void step_round(or_solver *s) {
     const int32_t W = s->W;
-    int64_t best_len = -1, best_id = -1;
     int32_t nt = 0;
+    s->n_pend = 0;
     /* phase 1: classify every visit against the snapshot, find winners */
     for (int64_t f = 0; f < s->frontier.n; ++f) {
         int32_t v = s->frontier.a[f];
@@ -508,11 +538,7 @@ static void step_round(or_solver *s) {
             s->st.literal_checks += ng_len(s, id);
             int c = classify(s, id, &u);
             if (c == 1) {
-                if (best_id < 0 || ng_len(s, id) < best_len ||
-                    (ng_len(s, id) == best_len && id < best_id)) {
-                    best_len = ng_len(s, id);
-                    best_id = id;
-                }
+                note_conflict(s, (int32_t)id);
             } else if (c == 2) {
                 int32_t x = var_of(u);
                 if (s->win[x] < 0) s->touched[nt++] = x;
@@ -533,13 +559,7 @@ static void step_round(or_solver *s) {
             int32_t id = m->a[q], u = 0;
             if (classify(s, id, &u) != 2) continue;
             int32_t x = var_of(u);
-            if (s->winsign[x] != -lit_sign(u)) {
-                if (best_id < 0 || ng_len(s, id) < best_len ||
-                    (ng_len(s, id) == best_len && id < best_id)) {
-                    best_len = ng_len(s, id);
-                    best_id = id;
-                }
-            }
+            if (s->winsign[x] != -lit_sign(u)) note_conflict(s, (int32_t)id);
         }
     }
     /* phase 3: Deps of each implied variable = OR of the Deps of the other
@@ -573,9 +593,9 @@ static void step_round(or_solver *s) {
     s->nass += nt;
     s->st.rounds += 1;
     s->st.propagations += nt;
-    if (best_id >= 0) {
+    if (s->n_pend > 0) {
         s->pend_kind = 1;
-        s->pend_id = (int32_t)best_id;
+        s->pend_id = s->pend_ids[0];
     }
 }
 
@@ -595,12 +615,12 @@ static int cmp_assigned(const void *a, const void *b) {
  * (sigma last) and *bj the highest level of the others (at least 1).
  * Returns 0, leaving nothing allocated, when sigma has no implying nogood
  * (a CompleteAssignment literal): the caller learns by Fwd-learning. */
-static int res_learn(or_solver *s, int32_t **outN, int64_t *outn, int32_t *outbj) {
+static int res_learn(or_solver *s, int32_t conf, int32_t **outN, int64_t *outn, int32_t *outbj) {
     s->epoch += 1;
     const int32_t ep = s->epoch;
     ivec d = {0};
-    const int32_t *L = ng_ptr(s, s->pend_id);
-    for (int32_t q = 0; q < ng_len(s, s->pend_id); ++q) {
+    const int32_t *L = ng_ptr(s, conf);
+    for (int32_t q = 0; q < ng_len(s, conf); ++q) {
         int32_t v = var_of(L[q]);
         if (s->mark[v] != ep) { s->mark[v] = ep; iv_push(&d, v); }
     }
@@ -644,8 +664,6 @@ static int res_learn(or_solver *s, int32_t **outN, int64_t *outn, int32_t *outbj
     return 1;
 }
 
-/* S6 + S7: Fwd-learning (Alg. 4) -- or Res-learning (Alg. 3) -- followed by
- * Backjump and assertion. */
 /* Restart: every variable is unassigned, the learned nogoods stay, and
  * InitialPropagation runs next. */
 static void restart(or_solver *s) {
@@ -660,38 +678,81 @@ static void restart(or_solver *s) {
     s->frontier.n = 0;
     s->pend_kind = 0;
     s->pend_id = -1;
+    s->n_pend = 0;
     s->need_init = 1;
     s->since_restart = 0;
     s->st.restarts += 1;
     fnv(s, 9);
 }
 
+/* B of a round conflict: the OR of the Deps of its variables */
+static void conflict_B(or_solver *s, int32_t conf, uint64_t *B) {
+    const int32_t W = s->W;
+    memset(B, 0, sizeof(uint64_t) * W);
+    const int32_t *L = ng_ptr(s, conf);
+    for (int32_t k = 0; k < ng_len(s, conf); ++k) {
+        int32_t y = var_of(L[k]);
+        for (int32_t q = 0; q < W; ++q) B[q] |= s->deps[(size_t)y * W + q];
+    }
+}
+
+/* A conflict that follows from level-1 facts alone (no answer set): under
+ * Fwd-learning B = 0; under Res-learning a round conflict with no literal
+ * above level 1.  conf >= 0 is a round conflict, -1 the pending gate
+ * conflict (its B is in pend_B). */
+static int at_root(or_solver *s, int32_t conf) {
+    if (conf >= 0 && s->learning == LEARN_RES) {
+        const int32_t *L = ng_ptr(s, conf);
+        for (int32_t k = 0; k < ng_len(s, conf); ++k)
+            if (s->lvl[var_of(L[k])] > 1) return 0;
+        return 1;
+    }
+    if (conf >= 0) conflict_B(s, conf, s->pend_B);
+    for (int32_t q = 0; q < s->W; ++q)
+        if (s->pend_B[q]) return 0;
+    return 1;
+}
+
+/* S6: the nogood learned from one conflict and its backjump level --
+ * Res-learning (Alg. 3) for a round conflict when selected, else (and when
+ * resolution reaches a literal without reason) Fwd-learning (Alg. 4): the
+ * decision literals of levels(B), ascending, and the second-highest level */
+static void learn_one(or_solver *s, int32_t conf, int32_t **outN, int64_t *outn,
+                      int32_t *outbj) {
+    if (conf >= 0 && s->learning == LEARN_RES && res_learn(s, conf, outN, outn, outbj)) return;
+    uint64_t *B = s->pend_B;
+    if (conf >= 0) conflict_B(s, conf, B);
+    /* levels(B), ascending: level l in 2..64W-1 for bit l-1, plus every
+     * level 64W..cdl when the saturated bit 64W-1 is set */
+    ivec lev = {0};
+    for (int32_t l = 2; l <= s->cdl; ++l) {
+        int32_t b = level_bit(s, l);
+        if ((B[b / 64] >> (b % 64)) & 1u) iv_push(&lev, l);
+    }
+    int64_t nN = lev.n;
+    int32_t *N = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nN > 0 ? nN : 1));
+    for (int64_t i = 0; i < nN; ++i) N[i] = s->dec[lev.a[i]];
+    *outbj = nN >= 2 ? lev.a[nN - 2] : 1;
+    free(lev.a);
+    *outN = N;
+    *outn = nN;
+}
+
+/* S6 + S7: Learning of the pending conflict -- or, with learn_conflicts > 1,
+ * of each selected round conflict in rank order -- then Backjump to the
+ * lowest backjump level among the learned nogoods and assertion of the
+ * latest literal of the first nogood that reaches it. */
 static void step_learn(or_solver *s, const or_limits *lim) {
     const int32_t W = s->W;
-    uint64_t *B = s->pend_B;
-    if (s->pend_kind == 1) {
-        memset(B, 0, sizeof(uint64_t) * W);
-        const int32_t *L = ng_ptr(s, s->pend_id);
-        for (int32_t k = 0; k < ng_len(s, s->pend_id); ++k) {
-            int32_t y = var_of(L[k]);
-            for (int32_t q = 0; q < W; ++q) B[q] |= s->deps[(size_t)y * W + q];
+    const int32_t n_sel = s->pend_kind == 1 ? s->n_pend : 1;
+    int32_t conf[8];
+    for (int32_t i = 0; i < n_sel; ++i) conf[i] = s->pend_kind == 1 ? s->pend_ids[i] : -1;
+    for (int32_t i = 0; i < n_sel; ++i)
+        if (at_root(s, conf[i])) {
+            s->st.conflicts += 1;
+            s->status = OR_UNSAT;
+            return;
         }
-    }
-    const int res = s->learning == LEARN_RES && s->pend_kind == 1;
-    int zero = 1;
-    if (res) {
-        /* a round conflict with no literal above level 1 holds at the root */
-        const int32_t *L = ng_ptr(s, s->pend_id);
-        for (int32_t k = 0; k < ng_len(s, s->pend_id); ++k) zero &= s->lvl[var_of(L[k])] <= 1;
-    } else {
-        for (int32_t q = 0; q < W; ++q) zero &= B[q] == 0;
-    }
-    if (zero) {
-        /* the conflict follows from level-1 facts alone */
-        s->st.conflicts += 1;
-        s->status = OR_UNSAT;
-        return;
-    }
     if (lim && lim->max_conflicts >= 0 && s->st.conflicts >= lim->max_conflicts) {
         s->status = OR_UNKNOWN;
         return;
@@ -705,89 +766,79 @@ static void step_learn(or_solver *s, const or_limits *lim) {
             fnv(s, 7);
         }
     }
-    int32_t *N = NULL, bj = 1;
-    int64_t nN = 0;
-    if (!(res && res_learn(s, &N, &nN, &bj))) {
-        /* levels(B), ascending: level l in 2..64W-1 for bit l-1, plus every
-         * level 64W..cdl when the saturated bit 64W-1 is set */
-        if (res) {
-            /* Res-learning fell back: the Deps of the conflict give B */
-            memset(B, 0, sizeof(uint64_t) * W);
-            const int32_t *L = ng_ptr(s, s->pend_id);
-            for (int32_t k = 0; k < ng_len(s, s->pend_id); ++k) {
-                int32_t y = var_of(L[k]);
-                for (int32_t q = 0; q < W; ++q) B[q] |= s->deps[(size_t)y * W + q];
+    int32_t *Nb = NULL, bjb = 0, idb = -1;
+    int64_t nb = 0;
+    for (int32_t i = 0; i < n_sel; ++i) {
+        int32_t *N = NULL, bj = 1;
+        int64_t nN = 0;
+        learn_one(s, conf[i], &N, &nN, &bj);
+        if ((lim && lim->learned_cap_ng >= 0 && s->n_learned + 1 > lim->learned_cap_ng) ||
+            (lim && lim->learned_cap_lits >= 0 && s->learned_lits + nN > lim->learned_cap_lits)) {
+            free(N);
+            free(Nb);
+            s->status = OR_UNKNOWN;
+            return;
+        }
+        const int32_t newid = (int32_t)(s->n0 + s->n_learned);
+        add_nogood(s, N, (int32_t)nN);
+        s->n_learned += 1;
+        s->learned_lits += nN;
+        s->st.learned += 1;
+        s->st.learned_len += nN;
+        if (s->decision == DEC_ACTIVITY) {
+            /* activity: every literal bumps its atom (an auxiliary variable
+             * of rule r stands for the head of r); halve all every 64 nogoods */
+            for (int64_t q = 0; q < nN; ++q) {
+                int32_t v = var_of(N[q]);
+                int32_t p = v <= s->A ? v : s->rhead[(v - s->A - 1) / 3];
+                s->act[p] += 8;
             }
+            if (s->st.learned % 64 == 0)
+                for (int32_t p = 0; p <= s->A; ++p) s->act[p] >>= 1;
         }
-        ivec lev = {0};
-        for (int32_t l = 2; l <= s->cdl; ++l) {
-            int32_t b = level_bit(s, l);
-            if ((B[b / 64] >> (b % 64)) & 1u) iv_push(&lev, l);
+        fnv(s, 2); fnv(s, conf[i]); fnv(s, (int32_t)nN); fnv(s, bj);
+        if (idb < 0 || bj < bjb) {
+            free(Nb);
+            Nb = N; nb = nN; bjb = bj; idb = newid;
+        } else {
+            free(N);
         }
-        nN = lev.n;
-        N = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nN > 0 ? nN : 1));
-        for (int64_t i = 0; i < nN; ++i) N[i] = s->dec[lev.a[i]];
-        bj = nN >= 2 ? lev.a[nN - 2] : 1;
-        free(lev.a);
     }
-    if ((lim && lim->learned_cap_ng >= 0 && s->n_learned + 1 > lim->learned_cap_ng) ||
-        (lim && lim->learned_cap_lits >= 0 && s->learned_lits + nN > lim->learned_cap_lits)) {
-        free(N);
-        s->status = OR_UNKNOWN;
-        return;
-    }
-    int32_t toplit = N[nN - 1];
-    const int32_t newid = (int32_t)(s->n0 + s->n_learned);
-    add_nogood(s, N, (int32_t)nN);
-    s->n_learned += 1;
-    s->learned_lits += nN;
-    s->st.learned += 1;
-    s->st.learned_len += nN;
-    if (s->decision == DEC_ACTIVITY) {
-        /* activity: every literal bumps its atom (an auxiliary variable of
-         * rule r stands for the head of r); halve all every 64 nogoods */
-        for (int64_t i = 0; i < nN; ++i) {
-            int32_t v = var_of(N[i]);
-            int32_t p = v <= s->A ? v : s->rhead[(v - s->A - 1) / 3];
-            s->act[p] += 8;
-        }
-        if (s->st.learned % 64 == 0)
-            for (int32_t p = 0; p <= s->A; ++p) s->act[p] >>= 1;
-    }
-    fnv(s, 2); fnv(s, s->pend_kind == 1 ? s->pend_id : -1); fnv(s, (int32_t)nN); fnv(s, bj);
     s->since_restart += 1;
     if (s->restart_every > 0 && s->since_restart >= s->restart_every) {
-        free(N);
+        free(Nb);
         restart(s);
         return;
     }
     /* Backjump: unassign everything above bj */
     for (int32_t v = 1; v <= s->V; ++v)
-        if (s->lvl[v] > bj) {
+        if (s->lvl[v] > bjb) {
             s->nass -= s->val[v] != 0;
             s->val[v] = 0;
             s->lvl[v] = 0;
             memset(s->deps + (size_t)v * W, 0, sizeof(uint64_t) * W);
         }
-    s->cdl = bj;
-    /* assert the complement of the latest decision at level bj */
-    int32_t x = var_of(toplit);
+    s->cdl = bjb;
+    /* assert the complement of the chosen nogood's latest literal at bj, its
+     * Deps those of the nogood's other variables */
+    int32_t toplit = Nb[nb - 1], x = var_of(toplit);
     s->nass += 1;
     s->val[x] = (int8_t)-lit_sign(toplit);
-    s->lvl[x] = bj;
+    s->lvl[x] = bjb;
     s->stamp[x] = s->clock++;
-    s->reason[x] = newid;
+    s->reason[x] = idb;
     uint64_t *d = s->deps + (size_t)x * W;
     memset(d, 0, sizeof(uint64_t) * W);
-    for (int64_t i = 0; i + 1 < nN; ++i) {
-        int32_t y = var_of(N[i]);
+    for (int64_t i = 0; i + 1 < nb; ++i) {
+        int32_t y = var_of(Nb[i]);
         for (int32_t q = 0; q < W; ++q) d[q] |= s->deps[(size_t)y * W + q];
     }
     s->frontier.n = 0;
     iv_push(&s->frontier, x);
     s->pend_kind = 0;
     s->pend_id = -1;
-    free(N);
+    s->n_pend = 0;
+    free(Nb);
 }
 
 /* S8: pick an applicable rule (T t_r in A, F n_r not in A, head unassigned)
@@ -1060,6 +1111,15 @@ int32_t or_set_enum(void *h, int64_t max_models, int64_t restart_every) {
     return 0;
 }
 
+/* Learn up to k (1..8) round conflicts per Learning step (ranked by length,
+ * then id), before the first step.  Returns 0, or OR_E_INVALID. */
+int32_t or_set_learn_conflicts(void *h, int32_t k) {
+    or_solver *s = (or_solver *)h;
+    if (s->last_step != ST_NONE || k < 1 || k > 8) return OR_E_INVALID;
+    s->learn_conflicts = k;
+    return 0;
+}
+
 /* the answer sets found so far: out[k*A + p-1] = 1 iff atom p is true in
  * the k-th (at most max_out of them); returns how many were found */
 int64_t or_models(void *h, uint8_t *out, int64_t max_out) {
@@ -1114,13 +1174,14 @@ int32_t or_solve(int32_t n_atoms, int32_t n_rules, const int32_t *head,
                  int32_t gate_mode, const or_limits *lim, uint8_t *model,
                  or_stats *st, const int32_t *score, int32_t fallback_after,
                  int32_t learning, int64_t max_models, int64_t restart_every,
-                 int32_t decision) {
+                 int32_t decision, int32_t learn_conflicts) {
     int32_t err = 0;
     void *h = or_create(n_atoms, n_rules, head, body_off, body_lits, W, gate_mode, &err);
     if (!h) return err;
     if (score) or_set_scores(h, score, fallback_after);
     if (or_set_learning(h, learning) != 0 || or_set_enum(h, max_models, restart_every) != 0 ||
-        (!score && or_set_decision(h, decision) != 0)) {
+        (!score && or_set_decision(h, decision) != 0) ||
+        or_set_learn_conflicts(h, learn_conflicts) != 0) {
         or_free(h);
         return OR_E_INVALID;
     }

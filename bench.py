@@ -260,6 +260,9 @@ def main():
     ap.add_argument("--no-enum", action="store_true", help="skip the several-answer-sets leg")
     ap.add_argument("--no-heur", action="store_true",
                     help="skip the Jeroslow-Wang and activity Decision legs")
+    ap.add_argument("--no-multi", action="store_true",
+                    help="skip the several-conflicts-per-step leg")
+    ap.add_argument("--multi-k", type=int, default=4, help="conflicts learned per step")
     ap.add_argument("--enum-models", type=int, default=16, help="answer sets asked per program")
     ap.add_argument("--res-steps", type=int, default=2)
     ap.add_argument("--graph-steps", type=int, default=2,
@@ -408,6 +411,9 @@ def main():
     if not args.no_heur:
         log("[bench] Jeroslow-Wang and activity Decision legs")
         line["heuristics"] = heur_leg(args, P, progs, verd, stream, dev, lim, ms_step, cth)
+    if not args.no_multi:
+        log("[bench] several-conflicts-per-step leg")
+        line["multi_learning"] = multi_leg(args, P, progs, verd, stream, dev, lim, ms_step, cth)
     if not args.no_enum:
         log("[bench] several-answer-sets leg")
         line["enum"] = enum_leg(args, P, progs, verd, stream, dev, lim, cth)
@@ -487,6 +493,38 @@ def heur_leg(args, P, progs, plain_verd, stream, dev, lim, plain_ms_step, cth):
         }
         del batch
         torch.cuda.empty_cache()
+    return out
+
+
+def multi_leg(args, P, progs, plain_verd, stream, dev, lim, plain_ms_step, cth):
+    """The same batch, budget and schedule learning up to --multi-k of each
+    round's conflicts per Learning step."""
+    import torch
+    gp = load_programs(progs, args.W, args.cap_ng, args.cap_lits, learn_conflicts=args.multi_k)
+    batch = P.Batch(gp, threads=args.threads, classes=args.classes, class_threads=cth)
+    with torch.cuda.stream(stream):
+        batch.bind(dev, stream=stream)
+    torch.cuda.synchronize()
+    ms, walls = timed_steps(batch, lim, 1, 1)
+    verd, models, stats = batch.results()
+    ms_step = float(np.sum(walls)) * 1000.0 / len(walls)
+    n_sat, n_unsat = int((verd == 1).sum()), int((verd == 2).sum())
+    n_sat_checked, bad = verify_models(progs, verd, models)
+    ips = (n_sat + n_unsat) / (ms_step / 1000.0)
+    plain_ips = int(((plain_verd == 1) | (plain_verd == 2)).sum()) / (plain_ms_step / 1000.0)
+    out = {
+        "learn_conflicts": args.multi_k, "ms_per_step": ms_step, "instances_per_s": ips,
+        "vs_one_conflict_instances_per_s": ips / plain_ips if plain_ips > 0 else None,
+        "verdicts": {"sat": n_sat, "unsat": n_unsat, "unknown": int((verd == 3).sum()),
+                     "error": int((verd < 0).sum())},
+        "verdict_contradictions_vs_one_conflict": int(
+            ((verd == 1) & (plain_verd == 2)).sum() + ((verd == 2) & (plain_verd == 1)).sum()),
+        "models_verified": {"sat": n_sat_checked, "not_stable": len(bad)},
+        "counters": search_counters(stats, ms_step),
+        "time_split": time_split(stats),
+    }
+    del batch
+    torch.cuda.empty_cache()
     return out
 
 

@@ -112,7 +112,15 @@ typedef struct {
                                   heuristic takes over for the rest of the
                                   search; < 0 never.  Default 10 */
     int32_t learning;          /* ASP_LEARN_FWD (default) or ASP_LEARN_RES */
-    int32_t reserved;          /* 0 */
+    int32_t learn_conflicts;   /* round conflicts learned per Learning step,
+                                  1..8 (0 means 1): the shortest, then
+                                  lowest-id, distinct conflicts of a round are
+                                  each learned on the same assignment, the
+                                  backjump goes to the lowest of their levels
+                                  and the first nogood reaching it asserts
+                                  (Sect. 4.2: the solver may select one or
+                                  more conflicts and takes the lowest target
+                                  level) */
     int64_t max_models;        /* answer sets asked for (the paper restarts the
                                   solver when more than one solution is
                                   requested, Sect. 3): 1 (default) is the
@@ -228,7 +236,8 @@ typedef struct {
  *  body_lits  : +a (atom a) or -a (not a), 1 <= a <= n_atoms
  *  opt        : NULL = {W=1, gate=UNFOUNDED, learned_cap_ng=1<<20,
  *               learned_cap_lits=1<<22, decision=OCC, fallback_after=10,
- *               learning=FWD, max_models=1, restart_every=0}
+ *               learning=FWD, learn_conflicts=1, max_models=1,
+ *               restart_every=0}
  * Repeated body literals are removed (first kept); a constraint holding both
  * a and not a is dropped.  Nogoods are generated per headed rule, then per
  * atom, then per constraint, and stably sorted by length (Sect. 4); their
@@ -314,8 +323,8 @@ int32_t asp_state_export(asp_program *prog, void *stream, asp_state *st);
 
 /* State import (the frontier must hold variables of level cdl; the pending
  * field may name a round conflict; learned nogoods must hold decision
- * literals T b_r only).  Fwd-learning programs with max_models = 1 and no
- * restarts only.  Errors: ASP_E_INVALID
+ * literals T b_r only).  Fwd-learning programs with max_models = 1, no
+ * restarts and one conflict learned per step only.  Errors: ASP_E_INVALID
  * on inconsistent input, ASP_E_CAPACITY beyond the learned-store capacity. */
 int32_t asp_state_import(asp_program *prog, void *stream, const asp_state *st);
 

@@ -33,7 +33,8 @@ class AspError(RuntimeError):
 class asp_options(C.Structure):
     _fields_ = [("W", C.c_int32), ("gate", C.c_int32), ("learned_cap_ng", C.c_int64),
                 ("learned_cap_lits", C.c_int64), ("decision", C.c_int32),
-                ("fallback_after", C.c_int32), ("learning", C.c_int32), ("reserved", C.c_int32),
+                ("fallback_after", C.c_int32), ("learning", C.c_int32),
+                ("learn_conflicts", C.c_int32),
                 ("max_models", C.c_int64), ("restart_every", C.c_int64)]
 
 
@@ -231,10 +232,10 @@ def limits(max_conflicts: int = -1, max_ms: int = 0) -> asp_limits:
 def options(W: int = 1, gate: int = GATE_UNFOUNDED, learned_cap_ng: int = 1 << 20,
             learned_cap_lits: int = 1 << 22, decision: int = DECISION_OCC,
             fallback_after: int = 10, learning: int = LEARN_FWD, max_models: int = 1,
-            restart_every: int = 0) -> asp_options:
+            restart_every: int = 0, learn_conflicts: int = 1) -> asp_options:
     return asp_options(int(W), int(gate), int(learned_cap_ng), int(learned_cap_lits),
-                       int(decision), int(fallback_after), int(learning), 0, int(max_models),
-                       int(restart_every))
+                       int(decision), int(fallback_after), int(learning), int(learn_conflicts),
+                       int(max_models), int(restart_every))
 
 
 @dataclass
@@ -264,12 +265,13 @@ class Program:
     def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED,
                  learned_cap_ng: int = 1 << 20, learned_cap_lits: int = 1 << 22,
                  decision: int = DECISION_OCC, fallback_after: int = 10,
-                 learning: int = LEARN_FWD, max_models: int = 1, restart_every: int = 0):
+                 learning: int = LEARN_FWD, max_models: int = 1, restart_every: int = 0,
+                 learn_conflicts: int = 1):
         self._head = np.ascontiguousarray(prog.head, np.int32)
         self._off = np.ascontiguousarray(prog.body_off, np.int64)
         self._lits = np.ascontiguousarray(prog.body_lits, np.int32)
         self.opt = options(W, gate, learned_cap_ng, learned_cap_lits, decision, fallback_after,
-                           learning, max_models, restart_every)
+                           learning, max_models, restart_every, learn_conflicts)
         self.sizes = asp_sizes()
         h = C.c_void_p()
         _check(lib().asp_load_program(int(prog.n_atoms), int(self._head.shape[0]),

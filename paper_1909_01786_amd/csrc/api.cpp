@@ -88,6 +88,7 @@ struct Plan {
     int32_t n = 0, threads = 256, W = 1, gate = 0, decision = 0, fallback_after = 10, learning = 0;
     int64_t Vmax = 0, Rhmax = 0, cap_ng = 0, cap_lits = 0;
     int64_t max_models = 1, restart_every = 0, model_store = 1;
+    int32_t learn_k = 1;
     std::vector<LaunchClass> classes;
     std::vector<InstDesc> desc;
     std::vector<int32_t> order;
@@ -167,7 +168,7 @@ asp_options default_options() {
     o.decision = ASP_DECISION_OCC;
     o.fallback_after = 10;
     o.learning = ASP_LEARN_FWD;
-    o.reserved = 0;
+    o.learn_conflicts = 1;
     o.max_models = 1;
     o.restart_every = 0;
     return o;
@@ -197,6 +198,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.cap_ng = opt.learned_cap_ng;
     P.cap_lits = opt.learned_cap_lits;
     P.max_models = opt.max_models;
+    P.learn_k = opt.learn_conflicts > 1 ? opt.learn_conflicts : 1;
     P.restart_every = opt.restart_every;
     P.model_store = opt.max_models > 0 ? opt.max_models : 1;
     P.desc.resize(P.n);
@@ -363,6 +365,7 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& 
     a.fallback_after = P.fallback_after;
     a.learning = P.learning;
     a.max_models = P.max_models;
+    a.learn_k = P.learn_k;
     a.restart_every = P.restart_every;
     a.model_store = P.model_store;
     a.words = lc.words;
@@ -698,6 +701,8 @@ int32_t asp_load_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
         return fail(ASP_E_INVALID, "unknown decision heuristic");
     if (o.learning != ASP_LEARN_FWD && o.learning != ASP_LEARN_RES)
         return fail(ASP_E_INVALID, "unknown learning step");
+    if (o.learn_conflicts < 0 || o.learn_conflicts > 8)
+        return fail(ASP_E_INVALID, "learn_conflicts must be in 0..8");
     if (o.max_models < 0 || o.max_models > ((int64_t)1 << 30) || o.restart_every < 0)
         return fail(ASP_E_INVALID, "max_models must be in 0..2^30, restart_every >= 0");
     if ((int64_t)n_atoms * (o.max_models > 0 ? o.max_models : 1) > ((int64_t)1 << 34))
@@ -963,7 +968,7 @@ int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
     if (p->opt.learning != ASP_LEARN_FWD)
         return fail(ASP_E_INVALID, "state import needs assignment stamps and reasons that "
                                    "Res-learning programs keep on the device only");
-    if (p->opt.max_models != 1 || p->opt.restart_every != 0)
+    if (p->opt.max_models != 1 || p->opt.restart_every != 0 || p->opt.learn_conflicts > 1)
         return fail(ASP_E_INVALID, "state import is for the plain search (one answer set, "
                                    "no restarts)");
     const int32_t V = p->hp.V, W = p->opt.W, A = p->hp.A, Rh = p->hp.Rh;
@@ -1126,7 +1131,8 @@ int32_t asp_batch_create(int32_t n, asp_program* const* progs, const asp_schedul
         if (o.W != b->opt.W || o.gate != b->opt.gate || o.learned_cap_ng != b->opt.learned_cap_ng ||
             o.learned_cap_lits != b->opt.learned_cap_lits || o.decision != b->opt.decision ||
             o.fallback_after != b->opt.fallback_after || o.learning != b->opt.learning ||
-            o.max_models != b->opt.max_models || o.restart_every != b->opt.restart_every)
+            o.max_models != b->opt.max_models || o.restart_every != b->opt.restart_every ||
+            std::max(o.learn_conflicts, 1) != std::max(b->opt.learn_conflicts, 1))
             return fail(ASP_E_INVALID, "batch programs must share their options");
         b->progs.push_back(&progs[i]->hp);
     }

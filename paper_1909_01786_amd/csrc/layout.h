@@ -56,6 +56,7 @@ struct SlotCtrl {
     int32_t status, init_done, last_step, use_score;
     int32_t consec, dec_open;                // learned-Decision fallback state
     int32_t epoch, exhausted;                // resolution marks; no answer set left
+    int32_t n_pend, pend_more[7];            // round conflicts selected for learning
     int64_t learned_lits;
     int64_t models, restarts, since_restart; // answer sets found, restarts
     int64_t rounds, visits, checks, props, decisions, conflicts, learned, learned_len,
@@ -182,7 +183,7 @@ struct KArgs {
     int32_t decision;            // DECISION_OCC, _SCORE, _JW or _ACTIVITY
     int32_t fallback_after;      // conflicts in a row before scores give way; <0 never
     int32_t learning;            // LEARN_FWD or LEARN_RES
-    int32_t pad1;
+    int32_t learn_k;             // round conflicts learned per step, 1..8
     int32_t words;               // LDS words per 2-bit map (this launch's largest V)
     int32_t step_mask;           // MODE_STEPS: kinds allowed to run (bit k)
     int64_t max_steps;           // MODE_STEPS: steps to run; MODE_SOLVE: guard

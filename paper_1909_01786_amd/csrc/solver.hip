@@ -63,6 +63,8 @@ struct Ctl {
     int32_t fr_ok;    // the LDS records describe the frontier trail[qh..qt)
     int32_t epoch;          // resolution-mark epoch (Res-learning)
     int32_t exhausted;      // the search showed no further answer set exists
+    int32_t n_pend;         // round conflicts selected for learning (pending, then pend_more)
+    int32_t pend_more[7];
     int64_t learned_lits, rounds, props, decisions, conflicts, learned, learned_len, gate_fail,
             completes, steps, visits, checks;
     int64_t models, restarts, since_restart;
@@ -75,6 +77,7 @@ struct Ctl {
 // LDS words through which lanes exchange per-phase results.
 struct Scr {
     unsigned long long conf_key;
+    unsigned long long conf_key2, conf_thr;   // conflict selection passes
     int32_t tail, clash, changed, pool_top, cap_err, nimpl;
     int32_t flag[kMaxWaves];
     int32_t wsum[kMaxWaves + 1];
@@ -115,8 +118,9 @@ struct Ctx {
     Scr* scr;
     int32_t W, T, tid, lane, wid, nw;
     int32_t decision, fallback_after, learning;
-    int32_t ext;            // extended search: several answer sets, restarts, activity
-                            // (compile-time in k_search)
+    int32_t ext;            // extended search: several answer sets, restarts, activity,
+                            // several conflicts learned per step (compile-time in k_search)
+    int32_t learn_k;        // round conflicts learned per step (extended search)
     unsigned long long my_visits, my_checks;
 };
 
@@ -401,6 +405,7 @@ DEV void reset_search(Ctx& c, Ctl& k) {
     k.fr_ok = 0;
     k.epoch = 0;
     k.exhausted = 0;
+    k.n_pend = 0;
     k.models = k.restarts = k.since_restart = 0;
     tab_clear_all(c);
     bar();
@@ -450,6 +455,8 @@ DEV void load_ctrl(Ctx& c, Ctl& k) {
     k.dec_open = uni(g.dec_open);
     k.epoch = uni(g.epoch);
     k.exhausted = uni(g.exhausted);
+    k.n_pend = uni(g.n_pend);
+    for (int i = 0; i < 7; ++i) k.pend_more[i] = uni(g.pend_more[i]);
     k.models = uni64(g.models);
     k.restarts = uni64(g.restarts);
     k.since_restart = uni64(g.since_restart);
@@ -505,6 +512,8 @@ DEV void save_ctrl(Ctx& c, const Ctl& k) {
     g.dec_open = k.dec_open;
     g.epoch = k.epoch;
     g.exhausted = k.exhausted;
+    g.n_pend = k.n_pend;
+    for (int i = 0; i < 7; ++i) g.pend_more[i] = k.pend_more[i];
     g.models = k.models;
     g.restarts = k.restarts;
     g.since_restart = k.since_restart;
@@ -646,9 +655,14 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
             }
         }
     }
+    // a conflict's key: pass 0 and 1 keep the smallest; a selection pass
+    // (2) the smallest above the keys already selected
+    auto note = [&](unsigned long long key) {
+        if (pass != 2) atomicMin(&c.scr->conf_key, key);
+        else if (key > c.scr->conf_thr) atomicMin(&c.scr->conf_key2, key);
+    };
     if (open == 0) {
-        if (pass == 0)
-            atomicMin(&c.scr->conf_key, ((unsigned long long)(uint32_t)len << 32) | (uint32_t)id);
+        if (pass != 1) note(((unsigned long long)(uint32_t)len << 32) | (uint32_t)id);
         return;
     }
     const int x = lvar(u);
@@ -717,8 +731,7 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
         const int t = tab_find(c, x);
         const unsigned long long key = t >= 0 ? c.tWin[t] : ld_wg(&c.win[x]);
         const uint32_t wcode = ((key >> 32) & 1ull) ? VF : VT;
-        if (wcode != code)
-            atomicMin(&c.scr->conf_key, ((unsigned long long)(uint32_t)len << 32) | (uint32_t)id);
+        if (wcode != code) note(((unsigned long long)(uint32_t)len << 32) | (uint32_t)id);
     }
 }
 
@@ -807,6 +820,23 @@ DEV void step_round(Ctx& c, Ctl& k) {
     if (uni(c.scr->clash)) {
         visit_pass(c, k, qh, qt, 1);
         bar();
+    }
+    // several conflicts learned per step: the next smallest keys, one
+    // selection pass each, on the same snapshot and winners
+    int nsel = 1;
+    if (c.ext && c.learn_k > 1) {
+        unsigned long long thr = (unsigned long long)uni64((int64_t)c.scr->conf_key);
+        for (int r = 1; r < c.learn_k && thr != ~0ull; ++r) {
+            c.scr->conf_key2 = ~0ull;       // identical from every lane
+            c.scr->conf_thr = thr;
+            bar();
+            visit_pass(c, k, qh, qt, 2);    // ends with a barrier
+            thr = (unsigned long long)uni64((int64_t)c.scr->conf_key2);
+            bar();                          // every lane has read it
+            if (thr == ~0ull) break;
+            k.pend_more[r - 1] = (int32_t)(uint32_t)(thr & 0xffffffffull);
+            nsel += 1;
+        }
     }
     const int nt = uni(c.scr->tail);
     // apply every implication, its Deps being the OR of the Deps of the
@@ -904,10 +934,11 @@ DEV void step_round(Ctx& c, Ctl& k) {
     if (ck != ~0ull) {
         k.pending = (int32_t)(uint32_t)(ck & 0xffffffffull);
         k.pend_kind = 1;
+        k.n_pend = nsel;
     }
 }
 
-// Res-learning (Alg. 3) of the pending round conflict at level `top`,
+// Res-learning (Alg. 3) of round conflict `conf` at level `top`,
 // resolution to the first UIP.  The trail is walked back one assigning step
 // at a time (a round, a decision, an assertion, a CompleteAssignment; gpos
 // gives the trail position where a variable's step begins, so (gpos,
@@ -922,13 +953,14 @@ DEV void step_round(Ctx& c, Ctl& k) {
 // 1; 0 when a variable to resolve has no implying nogood (a
 // CompleteAssignment literal: the caller learns by Fwd-learning); -1 when
 // the learned store is full; -2 on a broken invariant.
-DEV int res_learn(Ctx& c, Ctl& k, const KArgs& a, int base, int top, int* nN_out, int* bj_out) {
+DEV int res_learn(Ctx& c, Ctl& k, const KArgs& a, int conf, int base, int top, int* nN_out,
+                  int* bj_out) {
     const int T = c.T, tid = c.tid;
     const int ep = k.epoch + 1;
     k.epoch = ep;
     const int32_t* lits;
     int len;
-    ng_span(c, k, k.pending, lits, len);
+    ng_span(c, k, conf, lits, len);
     c.scr->tail = len;                         // identical from every lane
     unsigned long long at_top = 0ull;
     for (int q = tid; q < len; q += T) {
@@ -1110,6 +1142,7 @@ DEV void restart(Ctx& c, Ctl& k) {
     k.qh = k.qt = 0;
     k.pending = -1;
     k.pend_kind = 0;
+    k.n_pend = 0;
     k.init_done = 0;
     k.fr_ok = 0;
     k.since_restart = 0;
@@ -1118,27 +1151,30 @@ DEV void restart(Ctx& c, Ctl& k) {
     bar();
 }
 
-// Fwd-learning (Sect. 4.2, Alg. 4) -- or Res-learning (Alg. 3) -- +
-// Backjump + assertion.
-DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
+// B of a round conflict -- the OR of the Deps of its variables -- into sB.
+DEV void conflict_B(Ctx& c, Ctl& k, int conf) {
     const int T = c.T, tid = c.tid, W = c.W;
-    c.scr->pool_top = k.pool_top;
-    c.scr->cap_err = 0;
-    if (k.pend_kind == 1) {
-        // B = OR of the Deps of every variable of the conflict nogood
-        for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
-        bar();
-        const int32_t* lits;
-        int len;
-        ng_span(c, k, k.pending, lits, len);
-        for (int q = tid; q < len * W; q += T) {
-            int i = q / W, w = q - i * W;
-            unsigned long long d = c.deps[(size_t)lvar(lits[i]) * W + w];
-            if (d) atomicOr(&c.sB[w], d);
-        }
+    for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
+    bar();
+    const int32_t* lits;
+    int len;
+    ng_span(c, k, conf, lits, len);
+    for (int q = tid; q < len * W; q += T) {
+        int i = q / W, w = q - i * W;
+        unsigned long long d = c.deps[(size_t)lvar(lits[i]) * W + w];
+        if (d) atomicOr(&c.sB[w], d);
     }
     bar();
-    // every lane analyses B (W words) the same way
+}
+
+// The reading of B (W words in sB), identical in every lane: empty, the
+// saturated bit, the two highest level bits below it, the bit count.
+struct BRead {
+    bool zero, sat;
+    int hi1, hi2, npop;
+};
+DEV BRead read_B(Ctx& c) {
+    const int W = c.W;
     bool zero = true, sat = false;
     int hi1 = -1, hi2 = -1, npop = 0;
     for (int w = W - 1; w >= 0; --w) {
@@ -1157,28 +1193,118 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
             x &= ~(1ull << b);
         }
     }
-    zero = uni(zero ? 1 : 0) != 0;
-    sat = uni(sat ? 1 : 0) != 0;
-    hi1 = uni(hi1);
-    hi2 = uni(hi2);
-    npop = uni(npop);
-    const bool res = c.learning == LEARN_RES && k.pend_kind == 1;
-    int ctop = 0;
-    if (res) {
-        // Res-learning: a conflict with no literal above level 1 holds at the root
-        const int32_t* lits;
-        int len;
-        ng_span(c, k, k.pending, lits, len);
-        unsigned long long mx = 0ull;
-        for (int q = tid; q < len; q += T) {
-            const unsigned long long l = (unsigned long long)c.lvl[lvar(lits[q])];
-            mx = l > mx ? l : mx;
+    BRead r;
+    r.zero = uni(zero ? 1 : 0) != 0;
+    r.sat = uni(sat ? 1 : 0) != 0;
+    r.hi1 = uni(hi1);
+    r.hi2 = uni(hi2);
+    r.npop = uni(npop);
+    return r;
+}
+
+// The highest level among a round conflict's literals.
+DEV int conflict_top(Ctx& c, Ctl& k, int conf) {
+    const int32_t* lits;
+    int len;
+    ng_span(c, k, conf, lits, len);
+    unsigned long long mx = 0ull;
+    for (int q = c.tid; q < len; q += c.T) {
+        const unsigned long long l = (unsigned long long)c.lvl[lvar(lits[q])];
+        mx = l > mx ? l : mx;
+    }
+    return (int)block_max_u64(c, mx);
+}
+
+// The nogood learned from one conflict -- conf >= 0 a round conflict, -1
+// the gate's (its B in sB) -- written to the learned store at `base`:
+// Res-learning (Alg. 3) when selected, else (and when resolution reaches a
+// literal without implying nogood) Fwd-learning (Sect. 4.2, Alg. 4), the
+// decision literal of every level in levels(B) by increasing level.
+// have_B: sB already holds conf's B; ctop: the conflict's highest level,
+// or -1 to compute it.  Returns 0, or the status that ends the search.
+DEV int learn_one(Ctx& c, Ctl& k, const KArgs& a, int conf, bool have_B, int ctop, int base,
+                  int* nN_out, int* bj_out) {
+    const int T = c.T, tid = c.tid, W = c.W;
+    const int cdl = k.cdl;
+    if (conf >= 0 && c.learning == LEARN_RES) {
+        if (ctop < 0) ctop = conflict_top(c, k, conf);
+        const int got = res_learn(c, k, a, conf, base, ctop, nN_out, bj_out);
+        if (got < 0) return got == -1 ? ST_UNKNOWN : ST_E_INTERNAL;
+        if (got) return 0;
+        have_B = false;
+    }
+    if (conf >= 0 && !have_B) conflict_B(c, k, conf);
+    const BRead b = read_B(c);
+    int topl, bj, nN;
+    if (b.sat) {
+        topl = cdl;
+        bj = (cdl - 1 >= 64 * W) ? cdl - 1 : (b.hi1 >= 0 ? b.hi1 + 1 : 1);
+        nN = b.npop + (cdl - 64 * W + 1);
+    } else {
+        topl = b.hi1 + 1;
+        bj = b.hi2 >= 0 ? b.hi2 + 1 : 1;
+        nN = b.npop;
+    }
+    // Deps naming a level above cdl would be a broken invariant
+    if (b.hi1 + 1 > cdl || (b.sat && cdl < 64 * W) || topl < 2) return ST_E_INTERNAL;
+    if (k.n_learned + 1 > a.cap_ng || k.learned_lits + nN > a.cap_lits) return ST_UNKNOWN;
+    bar();
+    for (int w = tid; w < W; w += T) {
+        int pos = 0;
+        for (int w2 = 0; w2 < w; ++w2) {
+            unsigned long long y = c.sB[w2];
+            if (w2 == W - 1) y &= ~(1ull << 63);
+            if (w2 == 0) y &= ~1ull;
+            pos += __popcll(y);
         }
-        ctop = (int)block_max_u64(c, mx);
-        zero = ctop <= 1;
+        unsigned long long x = c.sB[w];
+        if (w == W - 1) x &= ~(1ull << 63);
+        if (w == 0) x &= ~1ull;
+        while (x) {
+            int bt = __ffsll((long long)x) - 1;
+            x &= x - 1ull;
+            c.llits[base + pos] = c.dec[w * 64 + bt + 1];
+            ++pos;
+        }
+    }
+    if (b.sat)
+        for (int l = 64 * W + tid; l <= cdl; l += T) c.llits[base + b.npop + (l - 64 * W)] = c.dec[l];
+    *nN_out = nN;
+    *bj_out = bj;
+    return 0;
+}
+
+// Learning of the pending conflict -- or, with several conflicts learned
+// per step, of each selected round conflict in rank order (Sect. 4.2: the
+// lowest backjump level among the learned nogoods is taken) -- then
+// Backjump and assertion of the latest literal of the first nogood that
+// reaches that level.
+DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
+    const int T = c.T, tid = c.tid, W = c.W;
+    c.scr->pool_top = k.pool_top;
+    c.scr->cap_err = 0;
+    const int nsel = (c.ext && k.pend_kind == 1) ? k.n_pend : 1;
+    auto conf_of = [&](int i) {
+        return k.pend_kind != 1 ? -1 : (i == 0 ? k.pending : k.pend_more[i - 1]);
+    };
+    // every selected conflict first: one that follows from level-1 facts
+    // alone (B = 0; under Res-learning no literal above level 1) is UNSAT
+    bool zero = false;
+    int ctop0 = -1;
+    for (int i = 0; i < nsel && !zero; ++i) {
+        const int conf = conf_of(i);
+        if (conf >= 0 && c.learning == LEARN_RES) {
+            const int t = conflict_top(c, k, conf);
+            if (i == 0) ctop0 = t;
+            zero = t <= 1;
+        } else {
+            if (conf >= 0) conflict_B(c, k, conf);
+            else bar();
+            zero = read_B(c).zero;
+            if (nsel > 1) bar();   // every lane has read B before another conflict's clears it
+        }
     }
     if (zero) {
-        // the conflict follows from level-1 facts alone
         k.conflicts += 1;
         k.status = ST_UNSAT;
         bar();
@@ -1200,96 +1326,57 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
             k.hash = fnv(k.hash, 7);
         }
     }
-    const int base = uni(c.loff[k.n_learned]);
-    const int cdl = k.cdl;
-    const int newid = k.nS + k.n_learned;
-    int bj = 1, nN = 0, got = 0;
-    if (res) {
-        got = res_learn(c, k, a, base, ctop, &nN, &bj);
-        if (got < 0) {
-            k.status = got == -1 ? ST_UNKNOWN : ST_E_INTERNAL;
+    int bj = 0, base = 0, nN = 0, newid = -1;   // the nogood that asserts
+    for (int i = 0; i < nsel; ++i) {
+        const int conf = conf_of(i);
+        const int ibase = uni(c.loff[k.n_learned]);
+        const int iid = k.nS + k.n_learned;
+        int inN = 0, ibj = 1;
+        const int st = learn_one(c, k, a, conf, nsel == 1, i == 0 ? ctop0 : -1, ibase, &inN, &ibj);
+        if (st) {
+            k.status = st;
             bar();
             return;
         }
-    }
-    if (!got) {
-        // Fwd-learning: the decision literal of every level in levels(B),
-        // by increasing level
-        int topl;
-        if (sat) {
-            topl = k.cdl;
-            bj = (k.cdl - 1 >= 64 * W) ? k.cdl - 1 : (hi1 >= 0 ? hi1 + 1 : 1);
-            nN = npop + (k.cdl - 64 * W + 1);
-        } else {
-            topl = hi1 + 1;
-            bj = hi2 >= 0 ? hi2 + 1 : 1;
-            nN = npop;
+        k.hash = fnv(k.hash, 2);
+        k.hash = fnv(k.hash, conf);
+        k.hash = fnv(k.hash, inN);
+        k.hash = fnv(k.hash, ibj);
+        c.loff[k.n_learned + 1] = ibase + inN;
+        bar();
+        add_occurrences(c, ibase, inN, iid);
+        k.n_learned += 1;
+        k.learned_lits += inN;
+        k.learned += 1;
+        k.learned_len += inN;
+        if (c.ext && c.decision == DECISION_ACTIVITY) {
+            // every literal bumps its atom (an auxiliary variable of rule r
+            // stands for the head of r); all are halved after every 64th nogood
+            for (int q = tid; q < inN; q += T) {
+                const int v = lvar(c.llits[ibase + q]);
+                atomicAdd(&c.act[v <= k.A ? v : c.RH[(v - k.A - 1) / 3]], 8);
+            }
+            if (k.learned % 64 == 0) {
+                bar();
+                for (int p = 1 + tid; p <= k.A; p += T) c.act[p] >>= 1;
+            }
         }
-        if (hi1 + 1 > k.cdl || (sat && k.cdl < 64 * W) || topl < 2) {
-            // Deps named a level above cdl: broken invariant
-            k.status = ST_E_INTERNAL;
-            bar();
-            return;
-        }
-        if (k.n_learned + 1 > a.cap_ng || k.learned_lits + nN > a.cap_lits) {
-            k.status = ST_UNKNOWN;
-            bar();
-            return;
+        if (newid < 0 || ibj < bj) {
+            bj = ibj;
+            base = ibase;
+            nN = inN;
+            newid = iid;
         }
         bar();
-        for (int w = tid; w < W; w += T) {
-            int pos = 0;
-            for (int w2 = 0; w2 < w; ++w2) {
-                unsigned long long y = c.sB[w2];
-                if (w2 == W - 1) y &= ~(1ull << 63);
-                if (w2 == 0) y &= ~1ull;
-                pos += __popcll(y);
-            }
-            unsigned long long x = c.sB[w];
-            if (w == W - 1) x &= ~(1ull << 63);
-            if (w == 0) x &= ~1ull;
-            while (x) {
-                int b = __ffsll((long long)x) - 1;
-                x &= x - 1ull;
-                c.llits[base + pos] = c.dec[w * 64 + b + 1];
-                ++pos;
-            }
-        }
-        if (sat)
-            for (int l = 64 * W + tid; l <= cdl; l += T) c.llits[base + npop + (l - 64 * W)] = c.dec[l];
-    }
-    k.hash = fnv(k.hash, 2);
-    k.hash = fnv(k.hash, k.pend_kind == 1 ? k.pending : -1);
-    k.hash = fnv(k.hash, nN);
-    k.hash = fnv(k.hash, bj);
-    c.loff[k.n_learned + 1] = base + nN;
-    bar();
-    add_occurrences(c, base, nN, newid);
-    if (c.ext && c.decision == DECISION_ACTIVITY) {
-        // every literal bumps its atom (an auxiliary variable of rule r
-        // stands for the head of r); all are halved after every 64th nogood
-        for (int i = tid; i < nN; i += T) {
-            const int v = lvar(c.llits[base + i]);
-            atomicAdd(&c.act[v <= k.A ? v : c.RH[(v - k.A - 1) / 3]], 8);
-        }
-        if ((k.learned + 1) % 64 == 0) {
-            bar();
-            for (int p = 1 + tid; p <= k.A; p += T) c.act[p] >>= 1;
-        }
     }
     k.since_restart += 1;
     if (c.ext && a.restart_every > 0 && k.since_restart >= a.restart_every) {
-        bar();
         k.pool_top = uni(c.scr->pool_top);
         if (uni(c.scr->cap_err)) {
             k.status = ST_E_CAPACITY;
             bar();
             return;
         }
-        k.n_learned += 1;
-        k.learned_lits += nN;
-        k.learned += 1;
-        k.learned_len += nN;
         restart(c, k);
         return;
     }
@@ -1339,10 +1426,7 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     k.fr_ok = 1;
     k.pending = -1;
     k.pend_kind = 0;
-    k.n_learned += 1;
-    k.learned_lits += nN;
-    k.learned += 1;
-    k.learned_len += nN;
+    k.n_pend = 0;
 }
 
 // Decision (Sect. 2): among rules with unassigned head, T t_r and not F n_r,
@@ -1710,6 +1794,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void 
     c.fallback_after = a.fallback_after;
     c.learning = LR;
     c.ext = EN;
+    c.learn_k = a.learn_k;
     c.T = MAXT;
     c.tid = threadIdx.x;
     c.lane = threadIdx.x & 63;
@@ -1790,7 +1875,8 @@ static hipError_t launch_v(const KArgs& a, int threads, int grid, size_t lds, hi
 }
 
 static int extended(const KArgs& a) {
-    return a.max_models != 1 || a.restart_every != 0 || a.decision == DECISION_ACTIVITY;
+    return a.max_models != 1 || a.restart_every != 0 || a.decision == DECISION_ACTIVITY ||
+           a.learn_k > 1;
 }
 
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {

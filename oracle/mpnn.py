@@ -95,6 +95,16 @@ def norm(s, n):
     return (s + half) >> k
 
 
+def bitlen(a: np.ndarray) -> np.ndarray:
+    """Bit length of non-negative integers (0 for 0), exactly."""
+    v = np.asarray(a, np.int64).copy()
+    n = np.zeros_like(v)
+    while (v > 0).any():
+        n += v > 0
+        v >>= 1
+    return n
+
+
 def features(g: Graph):
     V, A = g.V, g.A
     dpos = np.bincount(g.var[g.pos], minlength=V + 1).astype(np.int64)
@@ -107,8 +117,11 @@ def features(g: Graph):
     x[aux[kind == 0], 2] = 32
     x[aux[kind == 1], 3] = 32
     x[aux[kind == 2], 4] = 32
-    x[1:, 5] = rdiv(32, 1 + dpos[1:])
-    x[1:, 6] = rdiv(32, 1 + dneg[1:])
+    # degrees as saturating log codes: 16 * bit length (the occurrence
+    # heuristic ranks by the total degree, column 7)
+    x[1:, 5] = np.minimum(255, 16 * bitlen(dpos[1:]))
+    x[1:, 6] = np.minimum(255, 16 * bitlen(dneg[1:]))
+    x[1:, 7] = np.minimum(255, 16 * bitlen(dpos[1:] + dneg[1:]))
     lens = g.lens.astype(np.int64)
     npos = np.bincount(g.ng_of_lit[g.pos], minlength=g.n).astype(np.int64)
     y = np.zeros((g.n, F), np.int64)

@@ -200,8 +200,11 @@ __global__ __launch_bounds__(NT) void k_embed(ScorerArgs a) {
                 x[0] = 32;
                 x[1] = r <= d.A ? 32 : 0;
                 if (r > d.A) x[2 + (r - d.A - 1) % 3] = 32;
-                x[5] = (32 + (1 + dp) / 2) / (1 + dp);
-                x[6] = (32 + (1 + dn) / 2) / (1 + dn);
+                // degrees as saturating log codes: 16 * bit length
+                auto logc = [](int v) { return min(255, 16 * (v > 0 ? 32 - __clz(v) : 0)); };
+                x[5] = logc(dp);
+                x[6] = logc(dn);
+                x[7] = logc(dp + dn);
             } else if (tid < nrows && !var) {
                 const int32_t* NO = a.ng_off + d.ng_off;
                 const int32_t* NL = a.ng_lits + d.ng_lits;

@@ -120,7 +120,8 @@ struct Ctx {
     int32_t decision, fallback_after, learning;
     int32_t ext;            // extended search: several answer sets, restarts, activity,
                             // several conflicts learned per step (compile-time in k_search)
-    int32_t learn_k;        // round conflicts learned per step (extended search)
+    int32_t multi;          // several conflicts learned per step (compile-time in k_search)
+    int32_t learn_k;        // round conflicts learned per step
     unsigned long long my_visits, my_checks;
 };
 
@@ -824,7 +825,7 @@ DEV void step_round(Ctx& c, Ctl& k) {
     // several conflicts learned per step: the next smallest keys, one
     // selection pass each, on the same snapshot and winners
     int nsel = 1;
-    if (c.ext && c.learn_k > 1) {
+    if (c.multi && c.learn_k > 1) {
         unsigned long long thr = (unsigned long long)uni64((int64_t)c.scr->conf_key);
         for (int r = 1; r < c.learn_k && thr != ~0ull; ++r) {
             c.scr->conf_key2 = ~0ull;       // identical from every lane
@@ -1283,7 +1284,7 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     const int T = c.T, tid = c.tid, W = c.W;
     c.scr->pool_top = k.pool_top;
     c.scr->cap_err = 0;
-    const int nsel = (c.ext && k.pend_kind == 1) ? k.n_pend : 1;
+    const int nsel = (c.multi && k.pend_kind == 1) ? k.n_pend : 1;
     auto conf_of = [&](int i) {
         return k.pend_kind != 1 ? -1 : (i == 0 ? k.pending : k.pend_more[i - 1]);
     };
@@ -1780,9 +1781,10 @@ DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a, uint64_t t0) {
 
 // Three waves per SIMD: the register budget (168 VGPRs) at which the
 // search keeps six 128-thread workgroups resident per CU.  The Learning
-// step and the extended search (several answer sets, restarts, the
-// activity Decision) are compile-time parameters: the plain Fwd-learning
-// search carries none of the others' code or registers.
+// step and the search mode are compile-time parameters -- EN 0 plain, 1
+// extended (several answer sets, restarts, the activity Decision), 2 the
+// extended search learning several conflicts per step -- so each search
+// carries only its own code and registers.
 template <int MAXT, int LR, int EN>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void k_search(KArgs a) {
     HIP_DYNAMIC_SHARED(unsigned long long, smem64);  // 8-byte aligned base
@@ -1793,7 +1795,8 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void 
     c.decision = a.decision;
     c.fallback_after = a.fallback_after;
     c.learning = LR;
-    c.ext = EN;
+    c.ext = EN >= 1;
+    c.multi = EN == 2;
     c.learn_k = a.learn_k;
     c.T = MAXT;
     c.tid = threadIdx.x;
@@ -1874,17 +1877,23 @@ static hipError_t launch_v(const KArgs& a, int threads, int grid, size_t lds, hi
     return hipGetLastError();
 }
 
-static int extended(const KArgs& a) {
-    return a.max_models != 1 || a.restart_every != 0 || a.decision == DECISION_ACTIVITY ||
-           a.learn_k > 1;
+static int search_mode(const KArgs& a) {
+    if (a.learn_k > 1) return 2;
+    return (a.max_models != 1 || a.restart_every != 0 || a.decision == DECISION_ACTIVITY) ? 1 : 0;
+}
+
+template <int LR>
+static hipError_t launch_lr(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {
+    switch (search_mode(a)) {
+    case 0: return launch_v<LR, 0>(a, threads, grid, lds, s);
+    case 1: return launch_v<LR, 1>(a, threads, grid, lds, s);
+    default: return launch_v<LR, 2>(a, threads, grid, lds, s);
+    }
 }
 
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s) {
-    const int en = extended(a);
-    if (a.learning == LEARN_FWD) return en ? launch_v<LEARN_FWD, 1>(a, threads, grid, lds, s)
-                                           : launch_v<LEARN_FWD, 0>(a, threads, grid, lds, s);
-    if (a.learning == LEARN_RES) return en ? launch_v<LEARN_RES, 1>(a, threads, grid, lds, s)
-                                           : launch_v<LEARN_RES, 0>(a, threads, grid, lds, s);
+    if (a.learning == LEARN_FWD) return launch_lr<LEARN_FWD>(a, threads, grid, lds, s);
+    if (a.learning == LEARN_RES) return launch_lr<LEARN_RES>(a, threads, grid, lds, s);
     return hipErrorInvalidValue;
 }
 
@@ -1900,15 +1909,24 @@ static const void* search_fn_v(int threads) {
     }
 }
 
+template <int LR>
+static const void* search_fn_lr(int threads, int en) {
+    switch (en) {
+    case 0: return search_fn_v<LR, 0>(threads);
+    case 1: return search_fn_v<LR, 1>(threads);
+    default: return search_fn_v<LR, 2>(threads);
+    }
+}
+
 static const void* search_fn(int threads, int learning, int en) {
-    if (learning == LEARN_FWD) return en ? search_fn_v<LEARN_FWD, 1>(threads) : search_fn_v<LEARN_FWD, 0>(threads);
-    if (learning == LEARN_RES) return en ? search_fn_v<LEARN_RES, 1>(threads) : search_fn_v<LEARN_RES, 0>(threads);
+    if (learning == LEARN_FWD) return search_fn_lr<LEARN_FWD>(threads, en);
+    if (learning == LEARN_RES) return search_fn_lr<LEARN_RES>(threads, en);
     return nullptr;
 }
 
 hipError_t set_max_lds(int threads, size_t lds) {
     for (int lr : {(int)LEARN_FWD, (int)LEARN_RES})
-        for (int en = 0; en < 2; ++en) {
+        for (int en = 0; en < 3; ++en) {
             const void* f = search_fn(threads, lr, en);
             if (!f) return hipErrorInvalidValue;
             const hipError_t e =

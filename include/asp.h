@@ -401,9 +401,10 @@ int32_t asp_batch_get_scores(asp_batch *batch, int32_t i, int32_t *scores,
  *   layer l hc = act(hc S_l + norm(sum_{Tv in c} hv P_l + sum_{Fv in c} hv N_l, |c|) + bc_l)
  *           hv = act(hv T_l + norm(sum_{c with Tv} hc Q_l + sum_{c with Fv} hc R_l, deg v) + bv_l)
  *   score   s_v = hv wo + bo    (atoms v = 1..n_atoms)
- * Features, 32 standing for 1 and r(a, b) = (a + b/2) / b in integers:
- *   x_v = [32, 32*atom, 32*is_b, 32*is_t, 32*is_n, r(32, 1 + #c with Tv),
- *          r(32, 1 + #c with Fv), 0]
+ * Features, 32 standing for 1, r(a, b) = (a + b/2) / b in integers (0 for
+ * b = 0) and L(d) = min(255, 16 * bit length of d) a saturating log code:
+ *   x_v = [32, 32*atom, 32*is_b, 32*is_t, 32*is_n, L(#c with Tv),
+ *          L(#c with Fv), L(#c with Tv or Fv)]
  *   y_c = [32, r(32, |c|), 32*(|c|=1), 32*(|c|=2), 32*(|c|=3), 32*(|c|>=4),
  *          r(32 * #positive literals, |c|), 0]
  * Matrices are [in][out], row-major, bfloat16 bit patterns. */

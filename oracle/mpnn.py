@@ -23,10 +23,12 @@ arithmetic (all sums exact, >> is the arithmetic shift):
   readout  score_v = hv wo + bo            (the decision code of atom v <= A)
 
 Features (codes, 32 standing for 1): x_v = [32, 32 if v is an atom, 32 if
-v is some b_r, t_r, n_r (three entries), r(32, 1 + #nogoods with Tv),
-r(32, 1 + #nogoods with Fv), 0]; y_c = [32, r(32, |c|), 32 if |c| = 1, 2, 3,
->= 4 (four entries), r(32 #positive literals, |c|), 0], where
-r(a, b) = (a + b // 2) // b is a / b rounded half up (0 when b = 0).
+v is some b_r, t_r, n_r (three entries), L(#nogoods with Tv),
+L(#nogoods with Fv), L(#nogoods with Tv or Fv)]; y_c = [32, r(32, |c|),
+32 if |c| = 1, 2, 3, >= 4 (four entries), r(32 #positive literals, |c|), 0],
+where L(d) = min(255, 16 * bit length of d) is a saturating log code of a
+degree and r(a, b) = (a + b // 2) // b is a / b rounded half up (0 when
+b = 0).
 """
 from __future__ import annotations
 

@@ -24,7 +24,6 @@ namespace asp {
 size_t lds_bytes(int threads, int words);
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s);
 hipError_t set_max_lds(int threads, size_t lds);
-hipError_t occupancy(int threads, int learning, int en, size_t lds, int* blocks_per_cu);
 }  // namespace asp
 
 using namespace asp;

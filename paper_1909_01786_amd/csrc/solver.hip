@@ -1936,10 +1936,4 @@ hipError_t set_max_lds(int threads, size_t lds) {
     return hipSuccess;
 }
 
-hipError_t occupancy(int threads, int learning, int en, size_t lds, int* blocks_per_cu) {
-    const void* f = search_fn(threads, learning, en);
-    if (!f) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, threads, lds);
-}
-
 }  // namespace asp

@@ -36,7 +36,7 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "rounds", "visits", "literal_checks", "propagations", "decisions", "conflicts",
         "learned", "learned_len", "gate_failures", "completes", "models", "restarts")] + \
-        [("trace_hash", C.c_uint64)]
+        [("trace_hash", C.c_uint64), ("deps_reads", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -97,9 +97,11 @@ def lib():
         L.or_solve.argtypes = [C.c_int32, C.c_int32, i32p, i64p, i32p, C.c_int32, C.c_int32,
                                C.POINTER(Limits), np.ctypeslib.ndpointer(np.uint8, flags="C"),
                                C.POINTER(Stats), C.c_void_p, C.c_int32, C.c_int32, C.c_int64,
-                               C.c_int64, C.c_int32, C.c_int32]
+                               C.c_int64, C.c_int32, C.c_int32, C.c_int32]
         L.or_set_learn_conflicts.argtypes = [P, C.c_int32]
         L.or_set_learn_conflicts.restype = C.c_int32
+        L.or_set_lookahead.argtypes = [P, C.c_int32]
+        L.or_set_lookahead.restype = C.c_int32
         L.or_set_decision.argtypes = [P, C.c_int32]
         L.or_set_decision.restype = C.c_int32
         L.or_atom_scores.argtypes = [P, C.c_int32, i32p]
@@ -148,7 +150,7 @@ class Solver:
 
     def __init__(self, prog, W: int = 1, gate: int = GATE_UNFOUNDED, learning: int = LEARN_FWD,
                  max_models: int = 1, restart_every: int = 0, decision: int = DEC_OCC,
-                 learn_conflicts: int = 1):
+                 learn_conflicts: int = 1, lookahead: int = 0):
         L = lib()
         err = C.c_int32(0)
         self._h = L.or_create(int(prog.n_atoms), int(prog.n_rules),
@@ -167,6 +169,8 @@ class Solver:
             raise ValueError("decision must be DEC_OCC, DEC_JW or DEC_ACTIVITY")
         if L.or_set_learn_conflicts(self._h, int(learn_conflicts)) != 0:
             raise ValueError("learn_conflicts must be in 1..8")
+        if L.or_set_lookahead(self._h, int(lookahead)) != 0:
+            raise ValueError("lookahead must be in 0..8, with Fwd-learning")
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -266,7 +270,7 @@ class Solver:
 def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = None,
           scores=None, fallback_after: int = 10, learning: int = LEARN_FWD,
           max_models: int = 1, restart_every: int = 0, decision: int = DEC_OCC,
-          learn_conflicts: int = 1):
+          learn_conflicts: int = 1, lookahead: int = 0):
     """Encode and solve in one call; returns (status, model or None, stats).
     ``scores`` (int32[n_atoms + 1]) selects the score-driven Decision; the
     model is the first answer set found."""
@@ -285,18 +289,18 @@ def solve(prog, W: int = 1, gate: int = GATE_UNFOUNDED, limits: Limits | None = 
                     C.byref(limits) if limits else None, m, C.byref(st),
                     sc.ctypes.data if sc is not None else None, int(fallback_after),
                     int(learning), int(max_models), int(restart_every), int(decision),
-                    int(learn_conflicts))
+                    int(learn_conflicts), int(lookahead))
     return rc, (m[:A].copy() if rc == SAT else None), st.as_dict()
 
 
 def enumerate_models(prog, max_models: int = 0, restart_every: int = 0, W: int = 1,
                      gate: int = GATE_UNFOUNDED, learning: int = LEARN_FWD,
                      limits: Limits | None = None, decision: int = DEC_OCC,
-                     learn_conflicts: int = 1):
+                     learn_conflicts: int = 1, lookahead: int = 0):
     """Run the search for up to ``max_models`` answer sets (0: all); returns
     (status, list of answer sets in the order found, stats, exhausted)."""
     s = Solver(prog, W=W, gate=gate, learning=learning, max_models=max_models,
                restart_every=restart_every, decision=decision,
-               learn_conflicts=learn_conflicts)
+               learn_conflicts=learn_conflicts, lookahead=lookahead)
     rc = s.run(limits)
     return rc, s.models(), s.stats(), s.exhausted()

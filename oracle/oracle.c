@@ -104,6 +104,9 @@ typedef struct {
     int64_t rounds, visits, literal_checks, propagations, decisions, conflicts,
             learned, learned_len, gate_failures, completes, models, restarts;
     uint64_t trace_hash;
+    int64_t deps_reads;   /* measurement only: Deps words read to give the
+                             implied variables theirs, sum over propagations
+                             of (|winner| - 1) * W */
 } or_stats;
 
 typedef struct {
@@ -172,6 +175,7 @@ typedef struct {
     int32_t pend_ids[8];       /* the round conflicts selected for learning, ranked */
     int32_t n_pend;
     int32_t learn_conflicts;   /* round conflicts learned per Learning step, 1..8 */
+    int32_t lookahead;         /* Decision candidates tried by propagation, 0..8 (<= 1: off) */
     uint64_t *pend_B;
 
     int32_t status, last_step;
@@ -576,6 +580,7 @@ static void step_round(or_solver *s) {
             if (y == x) continue;
             for (int32_t q = 0; q < W; ++q) d[q] |= s->deps[(size_t)y * W + q];
         }
+        s->st.deps_reads += (int64_t)(ng_len(s, w) - 1) * W;
     }
     /* phase 4: apply every implication, even when a conflict was found */
     for (int32_t i = 0; i < nt; ++i) {
@@ -885,6 +890,95 @@ static void step_decide(or_solver *s, int32_t j) {
     fnv(s, 1); fnv(s, j);
 }
 
+/* Lookahead Decision (parallel lookahead, named in the Conclusions as a
+ * refinement to consider; this reading is the builder's): the K applicable
+ * rules with the highest (score of the head, -r) are tried in that order.  A
+ * trial decides T b_r at the next level and runs rounds until a fixpoint or
+ * a conflict.  A trial that ends in a conflict, or leaves every variable
+ * assigned, stands as the Decision (the search goes on from there: Learning,
+ * or the stability gate).  Otherwise the variables it assigned are counted
+ * and it is undone (everything above the current level unassigned).  When no
+ * trial stands, the candidate whose trial assigned the most variables (the
+ * earliest on ties) is decided.  Trial rounds count as rounds; an undone trial
+ * adds the events (10, rule, count) to the trace hash, and the Decision that
+ * stands or is taken adds (1, rule) and one decision. */
+static int32_t top_candidates(const or_solver *s, int32_t K, int32_t *out) {
+    const int32_t *sc = s->use_score ? s->score
+                      : s->decision == DEC_JW ? s->jw
+                      : s->decision == DEC_ACTIVITY ? s->act : s->occ;
+    int32_t n = 0;
+    int64_t keyv[8];
+    for (int32_t j = 0; j < s->Rh; ++j) {
+        int32_t p = s->rhead[j], t = s->A + 3 * j + 2, nn = s->A + 3 * j + 3;
+        if (s->val[p] != 0 || s->val[t] != 1 || s->val[nn] == -1) continue;
+        /* key (score, -j): insert into the sorted list of the best K */
+        int64_t key = (int64_t)sc[p] * ((int64_t)1 << 32) - j;
+        int32_t at = n;
+        while (at > 0 && keyv[at - 1] < key) --at;
+        if (at >= K) continue;
+        int32_t last = n < K ? n : K - 1;
+        for (int32_t q = last; q > at; --q) { keyv[q] = keyv[q - 1]; out[q] = out[q - 1]; }
+        keyv[at] = key;
+        out[at] = j;
+        if (n < K) ++n;
+    }
+    return n;
+}
+
+static void decide_raw(or_solver *s, int32_t j) {
+    const int32_t W = s->W;
+    int32_t b = s->A + 3 * j + 1;
+    s->cdl += 1;
+    s->dec[s->cdl] = b;
+    s->nass += 1;
+    s->val[b] = 1;
+    s->lvl[b] = s->cdl;
+    s->stamp[b] = s->clock++;
+    s->reason[b] = -1;
+    uint64_t *d = s->deps + (size_t)b * W;
+    memset(d, 0, sizeof(uint64_t) * W);
+    int32_t bit = level_bit(s, s->cdl);
+    d[bit / 64] |= 1ull << (bit % 64);
+    s->frontier.n = 0;
+    iv_push(&s->frontier, b);
+}
+
+static void step_lookahead(or_solver *s, int32_t j0) {
+    int32_t cand[8];
+    int32_t n = top_candidates(s, s->lookahead, cand);
+    if (n <= 1) { step_decide(s, j0); return; }
+    at_fixpoint(s);
+    const int32_t consec0 = s->consec, since0 = s->dec_since_conf, cdl0 = s->cdl;
+    const int64_t nass0 = s->nass;
+    int32_t best = -1;
+    int64_t best_p = -1;
+    for (int32_t i = 0; i < n; ++i) {
+        decide_raw(s, cand[i]);
+        s->dec_since_conf = 1;
+        while (s->frontier.n > 0 && s->pend_kind == 0) step_round(s);
+        if (s->pend_kind != 0 || s->nass == s->V) {
+            s->st.decisions += 1;
+            fnv(s, 1); fnv(s, cand[i]);
+            return;
+        }
+        const int64_t p = s->nass - nass0;
+        fnv(s, 10); fnv(s, cand[i]); fnv(s, (int32_t)p);
+        for (int32_t v = 1; v <= s->V; ++v) {
+            if (s->lvl[v] <= cdl0) continue;
+            s->val[v] = 0;
+            s->lvl[v] = 0;
+            memset(s->deps + (size_t)v * s->W, 0, sizeof(uint64_t) * s->W);
+        }
+        s->nass = nass0;
+        s->cdl = cdl0;
+        s->frontier.n = 0;
+        s->consec = consec0;
+        s->dec_since_conf = since0;
+        if (p > best_p) { best_p = p; best = cand[i]; }
+    }
+    step_decide(s, best);
+}
+
 /* S9: CompleteAssignment -- every unassigned original atom becomes false at
  * level cdl, depending on every decision made so far. */
 static void step_complete(or_solver *s) {
@@ -1014,7 +1108,10 @@ int32_t or_step(void *h, const or_limits *lim) {
     case ST_INIT: step_init(s); break;
     case ST_ROUND: step_round(s); break;
     case ST_LEARN: step_learn(s, lim); break;
-    case ST_DECIDE: step_decide(s, j); break;
+    case ST_DECIDE:
+        if (s->lookahead > 1) step_lookahead(s, j);
+        else step_decide(s, j);
+        break;
     case ST_COMPLETE: step_complete(s); break;
     case ST_GATE: step_gate(s, lim); break;
     default: return s->status;
@@ -1096,6 +1193,7 @@ void or_atom_scores(void *h, int32_t kind, int32_t *out) {
 int32_t or_set_learning(void *h, int32_t mode) {
     or_solver *s = (or_solver *)h;
     if (s->last_step != ST_NONE || (mode != LEARN_FWD && mode != LEARN_RES)) return OR_E_INVALID;
+    if (mode == LEARN_RES && s->lookahead > 1) return OR_E_INVALID;
     s->learning = mode;
     return 0;
 }
@@ -1117,6 +1215,14 @@ int32_t or_set_learn_conflicts(void *h, int32_t k) {
     or_solver *s = (or_solver *)h;
     if (s->last_step != ST_NONE || k < 1 || k > 8) return OR_E_INVALID;
     s->learn_conflicts = k;
+    return 0;
+}
+
+int32_t or_set_lookahead(void *h, int32_t k) {
+    or_solver *s = (or_solver *)h;
+    if (s->last_step != ST_NONE || k < 0 || k > 8) return OR_E_INVALID;
+    if (k > 1 && s->learning != LEARN_FWD) return OR_E_INVALID;
+    s->lookahead = k;
     return 0;
 }
 
@@ -1174,14 +1280,14 @@ int32_t or_solve(int32_t n_atoms, int32_t n_rules, const int32_t *head,
                  int32_t gate_mode, const or_limits *lim, uint8_t *model,
                  or_stats *st, const int32_t *score, int32_t fallback_after,
                  int32_t learning, int64_t max_models, int64_t restart_every,
-                 int32_t decision, int32_t learn_conflicts) {
+                 int32_t decision, int32_t learn_conflicts, int32_t lookahead) {
     int32_t err = 0;
     void *h = or_create(n_atoms, n_rules, head, body_off, body_lits, W, gate_mode, &err);
     if (!h) return err;
     if (score) or_set_scores(h, score, fallback_after);
     if (or_set_learning(h, learning) != 0 || or_set_enum(h, max_models, restart_every) != 0 ||
         (!score && or_set_decision(h, decision) != 0) ||
-        or_set_learn_conflicts(h, learn_conflicts) != 0) {
+        or_set_learn_conflicts(h, learn_conflicts) != 0 || or_set_lookahead(h, lookahead) != 0) {
         or_free(h);
         return OR_E_INVALID;
     }

@@ -10,7 +10,12 @@ same batch with these rows, program by program.
 
     python tests/golden/oracle_batch.py MODE [--workers N] [--n 4096]
 
-MODE: plain, jw, activity, multi4, enum16, look4, res.
+MODE: plain, jw, activity, multi4, enum16, look4, res.  Res-learning's long
+learned nogoods make some programs cost the oracle an hour or more, so
+"res" covers a sample: programs of every LDS size class (variables above
+32767, above 16383, above 4095, the rest) are taken in a seeded random
+order and each is run in a child process allowed RES_SECONDS; the first
+RES_PER_CLASS of each class that finish are kept.
 """
 from __future__ import annotations
 
@@ -43,6 +48,17 @@ MODES = {
 FIELDS = ("i", "status", "rounds", "visits", "literal_checks", "propagations", "decisions",
           "conflicts", "learned", "learned_len", "gate_failures", "completes", "models",
           "restarts", "exhausted", "trace_hash", "models_sha", "deps_reads")
+
+
+RES_PER_CLASS = 4
+RES_SECONDS = 240
+
+
+def lds_class(prog) -> int:
+    """LDS size class of a program by its variable count V = atoms + 3 *
+    headed rules (0 holds the largest)."""
+    V = int(prog.n_atoms) + 3 * int((np.asarray(prog.head) != 0).sum())
+    return 0 if V > 32767 else 1 if V > 16383 else 2 if V > 4095 else 3
 
 
 def path(mode: str, n: int = 4096) -> str:
@@ -95,6 +111,42 @@ def load(mode: str, n: int = 4096):
     return rows
 
 
+def res_sample(workers: int):
+    """Rows of the Res-learning sample (see the module docstring)."""
+    import json
+    import subprocess
+    rng = np.random.default_rng(7)
+    strata = [[] for _ in range(4)]
+    for i in rng.permutation(4096):
+        i = int(i)
+        strata[lds_class(aspgen.batch_random(i, batch_seed=SEED))].append(i)
+    code = ("import sys, json; sys.path.insert(0, %r); sys.path.insert(0, %r); "
+            "import oracle_batch as ob; print(json.dumps(ob.run_one(int(sys.argv[1]), 'res')))"
+            % (ROOT, HERE))
+
+    def attempt(i):
+        try:
+            out = subprocess.run([sys.executable, "-c", code, str(i)], capture_output=True,
+                                 text=True, timeout=RES_SECONDS)
+            return json.loads(out.stdout.strip().splitlines()[-1])
+        except subprocess.TimeoutExpired:
+            return None
+
+    rows = {}
+    for c, st in enumerate(strata):
+        got, tried = [], 0
+        with ThreadPoolExecutor(workers) as ex:
+            while len(got) < RES_PER_CLASS and tried < len(st):
+                batch = st[tried:tried + workers]
+                tried += len(batch)
+                for i, r in zip(batch, ex.map(attempt, batch)):
+                    if r is not None and len(got) < RES_PER_CLASS:
+                        got.append(i)
+                        rows[i] = r
+                print(f"res: class {c}: {len(got)} kept of {tried} tried", flush=True)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("mode", choices=sorted(MODES))
@@ -102,20 +154,23 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     args = ap.parse_args()
     oracle.build()
-    # largest programs first, so the pool ends together
-    sizes = [(aspgen.batch_random(i, batch_seed=SEED).body_lits.size, i) for i in range(args.n)]
-    order = [i for _, i in sorted(sizes, reverse=True)]
     t0 = time.time()
-    rows = {}
-    with ThreadPoolExecutor(args.workers) as ex:
-        for k, r in enumerate(ex.map(lambda i: run_one(i, args.mode), order)):
-            rows[r["i"]] = r
-            if (k + 1) % 256 == 0:
-                print(f"{args.mode}: {k + 1}/{args.n} in {time.time() - t0:.0f} s", flush=True)
+    if args.mode == "res":
+        rows = res_sample(args.workers)
+    else:
+        # largest programs first, so the pool ends together
+        sizes = [(aspgen.batch_random(i, batch_seed=SEED).body_lits.size, i) for i in range(args.n)]
+        order = [i for _, i in sorted(sizes, reverse=True)]
+        rows = {}
+        with ThreadPoolExecutor(args.workers) as ex:
+            for k, r in enumerate(ex.map(lambda i: run_one(i, args.mode), order)):
+                rows[r["i"]] = r
+                if (k + 1) % 256 == 0:
+                    print(f"{args.mode}: {k + 1}/{args.n} in {time.time() - t0:.0f} s", flush=True)
     tmp = path(args.mode, args.n) + ".tmp"
     with open(tmp, "w") as fh:
         fh.write(",".join(FIELDS) + "\n")
-        for i in range(args.n):
+        for i in sorted(rows):
             fh.write(",".join(str(rows[i][k]) for k in FIELDS) + "\n")
     os.replace(tmp, path(args.mode, args.n))
     print(f"{args.mode}: wrote {path(args.mode, args.n)} in {time.time() - t0:.0f} s")

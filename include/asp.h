@@ -308,6 +308,27 @@ int32_t asp_run_steps(asp_program *prog, void *stream, const asp_limits *lim,
 int32_t asp_solve(asp_program *prog, void *stream, const asp_limits *lim,
                   uint8_t *model, asp_stats *stats);
 
+/* Allocation-free form of asp_solve, for callers that cannot allocate
+ * device memory or bind an arena (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  The program's tables,
+ * its search state and the results live in a library-owned device array of
+ * ASP_NOALLOC_MAX_BYTES bytes, one per GPU, held from the first use until
+ * the process ends; the call uploads the program into it, solves on the
+ * current device with 256 threads, and copies the verdict, model (optional,
+ * n_atoms bytes, host) and stats (optional) back, like asp_solve.  It calls
+ * no device allocation or free.  Every call on one GPU uses that GPU's
+ * array, which keeps the last call's contents (nothing of it is read before
+ * the call writes it): calls that overlap on one GPU, from any stream or
+ * thread, race and must be serialised by the caller.  The program need not
+ * be bound, and a bound arena is left untouched.  Errors: ASP_E_CAPACITY
+ * when the program needs more than ASP_NOALLOC_MAX_BYTES (the learned-store
+ * capacities dominate: load with smaller learned_cap_lits / learned_cap_ng),
+ * ASP_E_INVALID for ASP_DECISION_SCORE programs (their scores need a bound
+ * arena), ASP_E_DEVICE on a HIP error.  Synchronous. */
+#define ASP_NOALLOC_MAX_BYTES (64u << 20)
+int32_t asp_solve_noalloc(const asp_program *prog, void *stream, const asp_limits *lim,
+                          uint8_t *model, asp_stats *stats);
+
 /* The answer sets found by the last search of a bound program, in the order
  * found: models (host, max_out * n_atoms bytes) gets the first
  * min(found, max(1, max_models), max_out), answer set k at k * n_atoms;

@@ -22,6 +22,7 @@ GATE_UNFOUNDED, GATE_ALLDEC = 0, 1
 DECISION_OCC, DECISION_SCORE, DECISION_JW, DECISION_ACTIVITY = 0, 1, 2, 3
 LEARN_FWD, LEARN_RES = 0, 1
 SCORER_F, SCORER_H, SCORER_L = 8, 64, 3
+NOALLOC_MAX_BYTES = 64 << 20   # ASP_NOALLOC_MAX_BYTES
 
 
 class AspError(RuntimeError):
@@ -136,7 +137,7 @@ EXPORTS = (
     "asp_batch_set_scores", "asp_batch_get_scores", "asp_scorer_workspace",
     "asp_batch_scorer_workspace", "asp_score_program", "asp_score_batch",
     "asp_batch_train_readout", "asp_batch_launch_info", "asp_solve_batch_graph",
-    "asp_get_models",
+    "asp_get_models", "asp_solve_noalloc",
 )
 
 _lib = None
@@ -161,6 +162,7 @@ def lib():
                                            C.POINTER(i32)]),
             "asp_run_steps": (i32, [P, P, C.POINTER(asp_limits), i64, C.POINTER(asp_stats)]),
             "asp_solve": (i32, [P, P, C.POINTER(asp_limits), P, C.POINTER(asp_stats)]),
+            "asp_solve_noalloc": (i32, [P, P, C.POINTER(asp_limits), P, C.POINTER(asp_stats)]),
             "asp_get_models": (i32, [P, P, P, i64, C.POINTER(i64)]),
             "asp_state_export": (i32, [P, P, C.POINTER(asp_state)]),
             "asp_state_import": (i32, [P, P, C.POINTER(asp_state)]),
@@ -356,6 +358,15 @@ class Program:
         s = asp_stats()
         st = _check(lib().asp_solve(self._h, _stream_ptr(self.stream),
                                     C.byref(lim) if lim else None, _ptr(m), C.byref(s)))
+        return st, (m[:self.n_atoms].copy() if st == SAT else None), s.as_dict()
+
+    def solve_noalloc(self, lim: asp_limits | None = None, stream=None):
+        """asp_solve_noalloc: the same solve in the library's own device
+        array (no arena; the program need not be bound)."""
+        m = np.zeros(max(self.n_atoms, 1), np.uint8)
+        s = asp_stats()
+        st = _check(lib().asp_solve_noalloc(self._h, _stream_ptr(stream),
+                                            C.byref(lim) if lim else None, _ptr(m), C.byref(s)))
         return st, (m[:self.n_atoms].copy() if st == SAT else None), s.as_dict()
 
     def models(self) -> list:

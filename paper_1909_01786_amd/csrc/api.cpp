@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -126,6 +127,7 @@ struct asp_program {
     uint8_t* arena = nullptr;
     uint64_t bytes = 0;
     Plan plan;
+    Plan load_plan;   // 256 threads, one class: fixed at load (allocation-free solve)
     int32_t threads = 256;
     ScorerPlan scorer;
 };
@@ -653,6 +655,64 @@ ScorerArgs scorer_args(const std::vector<const HostProgram*>& progs, const Plan&
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free solve
+// Device memory of asp_solve_noalloc: the program's tables, its search slot
+// and the results, laid out as a bound arena.  Each GPU the library runs on
+// holds its own copy until the process ends.  In host code `scratch` is only
+// a stand-in for the symbol: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) uint8_t scratch[ASP_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per
+// device, with that device current).
+int32_t scratch_base(uint8_t** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(ASP_E_DEVICE, "device index beyond 64");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(ASP_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                          hipGetErrorString(e));
+        g_scratch[dev] = (uint8_t*)ptr;
+    }
+    *out = g_scratch[dev];
+    return ASP_OK;
+}
+
+// Copy one program's static tables into an arena laid out by P, straight
+// from the program's own arrays (no staging buffers).
+int32_t upload_one(const HostProgram& h, const Plan& P, int32_t decision, uint8_t* arena,
+                   hipStream_t s) {
+    auto put = [&](uint64_t off, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(arena + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    const std::vector<int32_t>& ro = decision == ASP_DECISION_JW ? h.rule_jw : h.rule_occ;
+    HIPCHK(put(P.off_desc, P.desc.data(), sizeof(InstDesc) * P.desc.size()));
+    HIPCHK(put(P.off_order, P.order.data(), 4 * P.order.size()));
+    HIPCHK(put(P.off_slotoff, P.slot_off.data(), 8 * P.slot_off.size()));
+    HIPCHK(put(P.off_ngo, h.ng_off.data(), 4 * h.ng_off.size()));
+    HIPCHK(put(P.off_ngl, h.ng_lits.data(), 4 * h.ng_lits.size()));
+    HIPCHK(put(P.off_mo, h.map_off.data(), 4 * h.map_off.size()));
+    HIPCHK(put(P.off_mi, h.map_ent.data(), sizeof(MapEntry) * h.map_ent.size()));
+    HIPCHK(put(P.off_rh, h.rule_head.data(), 4 * h.rule_head.size()));
+    HIPCHK(put(P.off_ro, ro.data(), 4 * ro.size()));
+    HIPCHK(put(P.off_rbo, h.rb_off.data(), 4 * h.rb_off.size()));
+    HIPCHK(put(P.off_rbl, h.rb_lits.data(), 4 * h.rb_lits.size()));
+    return ASP_OK;
+}
+
+}  // namespace
+
 // ============================================================== C ABI
 extern "C" {
 
@@ -714,6 +774,7 @@ int32_t asp_load_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
     std::vector<const HostProgram*> one{&p->hp};
     rc = make_plan(one, o, 256, 1, p->plan);
     if (rc) return rc;
+    p->load_plan = p->plan;
     if (sizes) {
         sizes->n_atoms = p->hp.A;
         sizes->n_rules_headed = p->hp.Rh;
@@ -890,6 +951,44 @@ int32_t asp_solve(asp_program* p, void* stream, const asp_limits* lim, uint8_t* 
     const LaunchClass& lc = p->plan.classes[0];
     KArgs a = make_args(p->plan, p->arena, MODE_SOLVE, lc);
     apply_limits(a, p->plan, lim, di);
+    HIPCHK(launch_search(a, lc.threads, 1, lc.lds, s));
+    DevStats d;
+    int32_t verdict = 0;
+    HIPCHK(hipMemcpyAsync(&d, a.stats, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&verdict, a.verdicts, 4, hipMemcpyDeviceToHost, s));
+    if (model && p->hp.A > 0)
+        HIPCHK(hipMemcpyAsync(model, a.models, (size_t)p->hp.A, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats) to_stats(d, stats);
+    return verdict;
+}
+
+int32_t asp_solve_noalloc(const asp_program* p, void* stream, const asp_limits* lim,
+                          uint8_t* model, asp_stats* stats) {
+    if (!p) return fail(ASP_E_INVALID, "null program");
+    if (p->opt.decision == ASP_DECISION_SCORE)
+        return fail(ASP_E_INVALID, "score-driven Decision needs a bound arena (asp_set_scores)");
+    const Plan& P = p->load_plan;
+    if (P.total > (uint64_t)ASP_NOALLOC_MAX_BYTES)
+        return fail(ASP_E_CAPACITY, "program needs " + std::to_string(P.total) +
+                                        " bytes of device memory, the allocation-free solve has " +
+                                        std::to_string((uint64_t)ASP_NOALLOC_MAX_BYTES) +
+                                        " (lower learned_cap_lits / learned_cap_ng)");
+    uint8_t* base = nullptr;
+    int32_t rc = scratch_base(&base);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    DeviceInfo di = device_info();
+    rc = check_launch(P, di);
+    if (rc) return rc;
+    rc = upload_one(p->hp, P, p->opt.decision, base, s);
+    if (rc) return rc;
+    // the solve kernel resets every part of the slot it reads (MODE_SOLVE),
+    // and writes the verdict, the counters and the answer set it reports,
+    // so nothing left by an earlier call is read
+    const LaunchClass& lc = P.classes[0];
+    KArgs a = make_args(P, base, MODE_SOLVE, lc);
+    apply_limits(a, P, lim, di);
     HIPCHK(launch_search(a, lc.threads, 1, lc.lds, s));
     DevStats d;
     int32_t verdict = 0;

@@ -138,6 +138,20 @@ typedef struct {
                                   nogood and restarts instead of backjumping
                                   (the paper's restart option, Sect. 3);
                                   0 (default) never */
+    int32_t lookahead;         /* Fwd-learning only: 2..8 turns on the
+                                  lookahead Decision (parallel lookahead, a
+                                  refinement the Conclusions name): the
+                                  `lookahead` best applicable rules are each
+                                  tried -- decided and propagated to a
+                                  fixpoint or a conflict; a trial ending in a
+                                  conflict or a total assignment stands as
+                                  the Decision, the others are undone and
+                                  the one that assigned the most variables
+                                  (the best-scored on ties) is decided.
+                                  Trial rounds count as rounds; an undone
+                                  trial enters the trace hash as (10, rule,
+                                  count).  0 or 1 (default): off */
+    int32_t reserved;          /* 0 */
 } asp_options;
 
 /* Run limits. */
@@ -237,7 +251,7 @@ typedef struct {
  *  opt        : NULL = {W=1, gate=UNFOUNDED, learned_cap_ng=1<<20,
  *               learned_cap_lits=1<<22, decision=OCC, fallback_after=10,
  *               learning=FWD, learn_conflicts=1, max_models=1,
- *               restart_every=0}
+ *               restart_every=0, lookahead=0}
  * Repeated body literals are removed (first kept); a constraint holding both
  * a and not a is dropped.  Nogoods are generated per headed rule, then per
  * atom, then per constraint, and stably sorted by length (Sect. 4); their
@@ -476,6 +490,60 @@ int32_t asp_score_batch(asp_batch *batch, const asp_scorer_weights *w, void *ws,
 int32_t asp_batch_train_readout(asp_batch *batch, const asp_scorer_weights *w, void *ws,
                                 uint64_t ws_bytes, const int8_t *labels, int32_t steps,
                                 float lr, float *wb_out, float *loss_out, void *stream);
+
+/* ------------------------------------------- learned Decision training
+ * The scorer above is trained in its float form: activation a = code / 256
+ * in [0, 1], matrix and readout entries w = code / 128 in [-127/128,
+ * 127/128], layer and embedding biases b = code / 2^17, readout bias
+ * bo = code / 2^15, so that each layer is
+ *   a' = clamp(u / 4 + b, 0, 1),  u = (self term) + (edge sum) / 2^k
+ * -- the integer layer divided by 256, up to its roundings -- and the
+ * readout logit is a . wo + bo.  The float parameters are one vector of
+ * ASP_SCORER_NPARAM floats, in this order: Ev[8][64], Ec[8][64], ev[64],
+ * ec[64], P[3][64][64], N, S, Q, R, T (same shape), bc[3][64], bv[3][64],
+ * wo[64], bo.  Training minimises the mean binary cross-entropy of
+ * sigmoid(logit) against per-atom labels in [0, 1] over every layer, on the
+ * device: forward and backward passes with bfloat16 operands and float32
+ * accumulation on the matrix cores, full-batch Adam (beta 0.9 / 0.999,
+ * eps 1e-8), and after every step each parameter is clipped to the range its
+ * integer code can hold. */
+#define ASP_SCORER_NPARAM 75329
+
+/* Device workspace (bytes) for training on these programs: the graph (one
+ * row per variable and per static nogood, the literals as edges in both
+ * orders), features, labels, parameters and Adam state, and the
+ * activations of every layer (about 2.3 KB per row). */
+int32_t asp_scorer_train_workspace(int32_t n, asp_program *const *progs, uint64_t *bytes);
+
+/* Train on programs progs[0..n) with labels (host float, n_atoms per
+ * program in order; < 0 = no label).  params (host, ASP_SCORER_NPARAM):
+ * starting values in, trained values out.  steps = 0 runs one forward and
+ * backward pass only: loss_out[0] gets the loss and grad_out (optional,
+ * ASP_SCORER_NPARAM) the gradient, params unchanged.  steps > 0 runs that
+ * many Adam steps at learning rate lr: loss_out[t] (optional, steps floats)
+ * gets the loss before step t, grad_out (optional) the last gradient.
+ * ws: device memory of the workspace size, 256-byte aligned.  Errors:
+ * ASP_E_INVALID (no labelled atom, bad arguments), ASP_E_CAPACITY
+ * (workspace).  Synchronous. */
+int32_t asp_scorer_train(int32_t n, asp_program *const *progs, const float *labels,
+                         float *params, int32_t steps, float lr, void *ws, uint64_t ws_bytes,
+                         float *loss_out, float *grad_out, void *stream);
+
+/* Float parameters <-> integer weight codes (host only): codes are the
+ * parameters times their scale, rounded to nearest and clipped to the code
+ * ranges of asp_scorer_weights. */
+int32_t asp_scorer_quantize(const float *params, asp_scorer_weights *w);
+int32_t asp_scorer_dequantize(const asp_scorer_weights *w, float *params);
+
+/* The nogoods learned by instance i of the last batched solve (decision
+ * literals T b_r under Fwd-learning; any literals under Res-learning;
+ * answer-set blocking nogoods included), as CSR: *n_learned and *n_lits get
+ * the sizes; off (n_learned+1 entries) and lits (n_lits entries) are
+ * filled when not NULL and cap_ng / cap_lits hold them.  The conflict traces
+ * the learned Decision is trained on.  Synchronous. */
+int32_t asp_batch_learned(asp_batch *batch, int32_t i, int32_t *off, int64_t cap_ng,
+                          int32_t *lits, int64_t cap_lits, int32_t *n_learned,
+                          int64_t *n_lits, void *stream);
 
 /* ------------------------------------------------------------- misc */
 const char *asp_status_str(int32_t status);

@@ -22,6 +22,7 @@ GATE_UNFOUNDED, GATE_ALLDEC = 0, 1
 DECISION_OCC, DECISION_SCORE, DECISION_JW, DECISION_ACTIVITY = 0, 1, 2, 3
 LEARN_FWD, LEARN_RES = 0, 1
 SCORER_F, SCORER_H, SCORER_L = 8, 64, 3
+SCORER_NPARAM = 75329          # ASP_SCORER_NPARAM: float parameters of the trainable scorer
 NOALLOC_MAX_BYTES = 64 << 20   # ASP_NOALLOC_MAX_BYTES
 
 
@@ -36,7 +37,8 @@ class asp_options(C.Structure):
                 ("learned_cap_lits", C.c_int64), ("decision", C.c_int32),
                 ("fallback_after", C.c_int32), ("learning", C.c_int32),
                 ("learn_conflicts", C.c_int32),
-                ("max_models", C.c_int64), ("restart_every", C.c_int64)]
+                ("max_models", C.c_int64), ("restart_every", C.c_int64),
+                ("lookahead", C.c_int32), ("reserved", C.c_int32)]
 
 
 class asp_limits(C.Structure):
@@ -128,6 +130,65 @@ def scorer_weights(w: dict) -> asp_scorer_weights:
     return out
 
 
+def weights_dict(w: asp_scorer_weights) -> dict:
+    """Unpack asp_scorer_weights into integer codes ([in, out] matrices)."""
+    def codes(name, shape):
+        bits = np.ctypeslib.as_array(getattr(w, name)).astype(np.uint32) << 16
+        return bits.view(np.float32).astype(np.int64).reshape(shape)
+    out = {"Ev": codes("Ev", (SCORER_F, SCORER_H)), "Ec": codes("Ec", (SCORER_F, SCORER_H))}
+    for k in ("P", "N", "S", "Q", "R", "T"):
+        out[k] = codes(k, (SCORER_L, SCORER_H, SCORER_H))
+    out["ev"] = np.ctypeslib.as_array(w.ev).astype(np.int64).copy()
+    out["ec"] = np.ctypeslib.as_array(w.ec).astype(np.int64).copy()
+    out["bc"] = np.ctypeslib.as_array(w.bc).astype(np.int64).reshape(SCORER_L, SCORER_H).copy()
+    out["bv"] = np.ctypeslib.as_array(w.bv).astype(np.int64).reshape(SCORER_L, SCORER_H).copy()
+    out["wo"] = np.ctypeslib.as_array(w.wo).astype(np.int64).copy()
+    out["bo"] = int(w.bo)
+    return out
+
+
+def quantize(params) -> dict:
+    """Float scorer parameters -> integer weight codes (asp_scorer_quantize)."""
+    p = np.ascontiguousarray(params, np.float32)
+    if p.shape != (SCORER_NPARAM,):
+        raise ValueError(f"expected {SCORER_NPARAM} parameters")
+    w = asp_scorer_weights()
+    _check(lib().asp_scorer_quantize(_ptr(p), C.byref(w)))
+    return weights_dict(w)
+
+
+def dequantize(w: dict) -> np.ndarray:
+    """Integer weight codes -> float scorer parameters (asp_scorer_dequantize)."""
+    packed = w if isinstance(w, asp_scorer_weights) else scorer_weights(w)
+    p = np.zeros(SCORER_NPARAM, np.float32)
+    _check(lib().asp_scorer_dequantize(C.byref(packed), _ptr(p)))
+    return p
+
+
+def train_scorer(programs, labels, params, steps: int, lr: float = 1e-3, device="cuda",
+                 stream=None, ws=None):
+    """Train the scorer on the device (asp_scorer_train).  labels: one float
+    array per program over its atoms 1..A (< 0: no label).  steps = 0: one
+    gradient pass.  Returns (params, losses, grad)."""
+    progs = list(programs)
+    arr = (C.c_void_p * len(progs))(*[p._h.value for p in progs])
+    lab = np.ascontiguousarray(np.concatenate([np.asarray(l, np.float32).reshape(-1)
+                                               for l in labels]), np.float32)
+    if lab.shape[0] != sum(p.n_atoms for p in progs):
+        raise ValueError("labels must hold n_atoms entries per program")
+    if ws is None:
+        nb = C.c_uint64(0)
+        _check(lib().asp_scorer_train_workspace(len(progs), C.cast(arr, C.c_void_p), C.byref(nb)))
+        ws = _arena(nb.value, device)
+    p = np.ascontiguousarray(params, np.float32).copy()
+    loss = np.zeros(max(int(steps), 1), np.float32)
+    grad = np.zeros(SCORER_NPARAM, np.float32)
+    _check(lib().asp_scorer_train(len(progs), C.cast(arr, C.c_void_p), _ptr(lab), _ptr(p),
+                                  int(steps), float(lr), C.c_void_p(ws.data_ptr()),
+                                  int(ws.numel()), _ptr(loss), _ptr(grad), _stream_ptr(stream)))
+    return p, loss, grad
+
+
 EXPORTS = (
     "asp_load_program", "asp_free_program", "asp_program_nogoods", "asp_bind_device",
     "asp_propagate", "asp_analyze_conflict", "asp_run_steps", "asp_solve",
@@ -137,7 +198,8 @@ EXPORTS = (
     "asp_batch_set_scores", "asp_batch_get_scores", "asp_scorer_workspace",
     "asp_batch_scorer_workspace", "asp_score_program", "asp_score_batch",
     "asp_batch_train_readout", "asp_batch_launch_info", "asp_solve_batch_graph",
-    "asp_get_models", "asp_solve_noalloc",
+    "asp_get_models", "asp_solve_noalloc", "asp_scorer_train_workspace", "asp_scorer_train",
+    "asp_scorer_quantize", "asp_scorer_dequantize", "asp_batch_learned",
 )
 
 _lib = None
@@ -187,6 +249,11 @@ def lib():
             "asp_score_batch": (i32, [P, C.POINTER(asp_scorer_weights), P, u64, P]),
             "asp_batch_train_readout": (i32, [P, C.POINTER(asp_scorer_weights), P, u64, P, i32,
                                               C.c_float, P, P, P]),
+            "asp_scorer_train_workspace": (i32, [i32, P, C.POINTER(u64)]),
+            "asp_scorer_train": (i32, [i32, P, P, P, i32, C.c_float, P, u64, P, P, P]),
+            "asp_scorer_quantize": (i32, [P, C.POINTER(asp_scorer_weights)]),
+            "asp_scorer_dequantize": (i32, [C.POINTER(asp_scorer_weights), P]),
+            "asp_batch_learned": (i32, [P, i32, P, i64, P, i64, C.POINTER(i32), C.POINTER(i64), P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -234,10 +301,10 @@ def limits(max_conflicts: int = -1, max_ms: int = 0) -> asp_limits:
 def options(W: int = 1, gate: int = GATE_UNFOUNDED, learned_cap_ng: int = 1 << 20,
             learned_cap_lits: int = 1 << 22, decision: int = DECISION_OCC,
             fallback_after: int = 10, learning: int = LEARN_FWD, max_models: int = 1,
-            restart_every: int = 0, learn_conflicts: int = 1) -> asp_options:
+            restart_every: int = 0, learn_conflicts: int = 1, lookahead: int = 0) -> asp_options:
     return asp_options(int(W), int(gate), int(learned_cap_ng), int(learned_cap_lits),
                        int(decision), int(fallback_after), int(learning), int(learn_conflicts),
-                       int(max_models), int(restart_every))
+                       int(max_models), int(restart_every), int(lookahead), 0)
 
 
 @dataclass
@@ -268,12 +335,12 @@ class Program:
                  learned_cap_ng: int = 1 << 20, learned_cap_lits: int = 1 << 22,
                  decision: int = DECISION_OCC, fallback_after: int = 10,
                  learning: int = LEARN_FWD, max_models: int = 1, restart_every: int = 0,
-                 learn_conflicts: int = 1):
+                 learn_conflicts: int = 1, lookahead: int = 0):
         self._head = np.ascontiguousarray(prog.head, np.int32)
         self._off = np.ascontiguousarray(prog.body_off, np.int64)
         self._lits = np.ascontiguousarray(prog.body_lits, np.int32)
         self.opt = options(W, gate, learned_cap_ng, learned_cap_lits, decision, fallback_after,
-                           learning, max_models, restart_every, learn_conflicts)
+                           learning, max_models, restart_every, learn_conflicts, lookahead)
         self.sizes = asp_sizes()
         h = C.c_void_p()
         _check(lib().asp_load_program(int(prog.n_atoms), int(self._head.shape[0]),
@@ -507,6 +574,19 @@ class Batch:
         bound on a non-default stream)."""
         f = lib().asp_solve_batch_graph if graph else lib().asp_solve_batch
         _check(f(self._h, _stream_ptr(self.stream), C.byref(lim) if lim else None))
+
+    def learned(self, i: int):
+        """(offsets, literals) of the nogoods instance i learned in the last
+        solve (asp_batch_learned)."""
+        n, nl = C.c_int32(0), C.c_int64(0)
+        _check(lib().asp_batch_learned(self._h, int(i), None, 0, None, 0, C.byref(n),
+                                       C.byref(nl), _stream_ptr(self.stream)))
+        off = np.zeros(n.value + 1, np.int32)
+        lits = np.zeros(max(nl.value, 1), np.int32)
+        _check(lib().asp_batch_learned(self._h, int(i), _ptr(off), off.shape[0], _ptr(lits),
+                                       lits.shape[0], C.byref(n), C.byref(nl),
+                                       _stream_ptr(self.stream)))
+        return off, lits[:nl.value]
 
     def launch_info(self):
         """[(first, count, threads, ms)] per launch class, and the instance order."""

@@ -2,8 +2,8 @@
 
 The library is the product path: ``csrc/encode.cpp`` (host encoding),
 ``csrc/solver.hip`` (device search), ``csrc/scorer.hip`` (learned Decision
-scorer) and ``csrc/api.cpp`` (C ABI of
-``include/asp.h``).  Packed FP32 instructions are disabled for every HIP
+scorer), ``csrc/trainer.hip`` and ``csrc/train.cpp`` (its training) and
+``csrc/api.cpp`` (C ABI of ``include/asp.h``).  Packed FP32 instructions are disabled for every HIP
 translation unit.
 """
 from __future__ import annotations
@@ -11,13 +11,14 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libasp.so")
-SOURCES = ["encode.cpp", "api.cpp", "solver.hip", "scorer.hip"]
-HEADERS = ["encode.h", "layout.h"]
+SOURCES = ["encode.cpp", "api.cpp", "train.cpp", "solver.hip", "scorer.hip", "trainer.hip"]
+HEADERS = ["encode.h", "layout.h", "scorer.h", "train.h", "trainer.h"]
 ARCH = os.environ.get("ASP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -30,15 +31,19 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libasp.so (always recompiles)."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") or src in ("api.cpp", "encode.cpp") else []
-        cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        lang = ["-x", "hip"]
+        cmds.append([HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    # the translation units compile independently, in parallel
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+    with ThreadPoolExecutor(len(cmds)) as ex:
+        list(ex.map(run, cmds))
     tmp = f"{LIB}.tmp{os.getpid()}"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <memory>
 #include <mutex>
@@ -20,6 +21,7 @@
 #include "encode.h"
 #include "layout.h"
 #include "scorer.h"
+#include "train.h"
 
 namespace asp {
 size_t lds_bytes(int threads, int words);
@@ -89,6 +91,7 @@ struct Plan {
     int64_t Vmax = 0, Rhmax = 0, cap_ng = 0, cap_lits = 0;
     int64_t max_models = 1, restart_every = 0, model_store = 1;
     int32_t learn_k = 1;
+    int32_t lookahead = 0;
     std::vector<LaunchClass> classes;
     std::vector<InstDesc> desc;
     std::vector<int32_t> order;
@@ -172,6 +175,8 @@ asp_options default_options() {
     o.learn_conflicts = 1;
     o.max_models = 1;
     o.restart_every = 0;
+    o.lookahead = 0;
+    o.reserved = 0;
     return o;
 }
 
@@ -201,6 +206,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.max_models = opt.max_models;
     P.learn_k = opt.learn_conflicts > 1 ? opt.learn_conflicts : 1;
     P.restart_every = opt.restart_every;
+    P.lookahead = opt.lookahead > 1 ? opt.lookahead : 0;
     P.model_store = opt.max_models > 0 ? opt.max_models : 1;
     P.desc.resize(P.n);
     P.slot_off.resize(P.n);
@@ -369,6 +375,7 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& 
     a.learn_k = P.learn_k;
     a.restart_every = P.restart_every;
     a.model_store = P.model_store;
+    a.lookahead = P.lookahead;
     a.words = lc.words;
     a.step_mask = 0;
     a.max_steps = -1;
@@ -762,6 +769,10 @@ int32_t asp_load_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
         return fail(ASP_E_INVALID, "unknown learning step");
     if (o.learn_conflicts < 0 || o.learn_conflicts > 8)
         return fail(ASP_E_INVALID, "learn_conflicts must be in 0..8");
+    if (o.lookahead < 0 || o.lookahead > 8)
+        return fail(ASP_E_INVALID, "lookahead must be in 0..8");
+    if (o.lookahead > 1 && o.learning != ASP_LEARN_FWD)
+        return fail(ASP_E_INVALID, "the lookahead Decision needs Fwd-learning");
     if (o.max_models < 0 || o.max_models > ((int64_t)1 << 30) || o.restart_every < 0)
         return fail(ASP_E_INVALID, "max_models must be in 0..2^30, restart_every >= 0");
     if ((int64_t)n_atoms * (o.max_models > 0 ? o.max_models : 1) > ((int64_t)1 << 34))
@@ -1058,6 +1069,31 @@ int32_t asp_state_export(asp_program* p, void* stream, asp_state* st) {
         if (k.cdl >= 1) st->dec[1] = 0;
     }
     if (st->frontier) std::sort(st->frontier, st->frontier + (k.qt - k.qh));
+    if (p->opt.learning == ASP_LEARN_FWD && (st->lvl || st->deps)) {
+        // The Fwd-learning search keeps no per-variable levels and leaves the
+        // Deps of unassigned variables stale: the trail is in assignment
+        // order and level l (2..cdl) begins at tlim[l], so a variable's level
+        // is the highest l <= cdl whose segment starts at or before its trail
+        // position (1 below tlim[2]); unassigned variables get level 0 and
+        // empty Deps.
+        std::vector<int32_t> trail((size_t)std::max(k.qt, 0)), tlim((size_t)k.cdl + 2, 0);
+        HIPCHK(get(trail.data(), L.trail, 4 * trail.size()));
+        HIPCHK(get(tlim.data(), L.tlim, 4 * tlim.size()));
+        std::vector<int8_t> val((size_t)V + 1);
+        HIPCHK(get(val.data(), L.val8, (size_t)V + 1));
+        HIPCHK(hipStreamSynchronize(s));
+        if (st->lvl) {
+            std::fill(st->lvl, st->lvl + V + 1, 0);
+            int32_t l = 1;
+            for (int32_t q = 0; q < k.qt; ++q) {
+                while (l < k.cdl && tlim[l + 1] <= q) ++l;
+                st->lvl[trail[q]] = l;
+            }
+        }
+        if (st->deps)
+            for (int32_t v = 0; v <= V; ++v)
+                if (val[v] == 0) std::fill(st->deps + (size_t)v * W, st->deps + (size_t)(v + 1) * W, 0ull);
+    }
     return ASP_OK;
 }
 
@@ -1066,7 +1102,8 @@ int32_t asp_state_import(asp_program* p, void* stream, const asp_state* st) {
     if (p->opt.learning != ASP_LEARN_FWD)
         return fail(ASP_E_INVALID, "state import needs assignment stamps and reasons that "
                                    "Res-learning programs keep on the device only");
-    if (p->opt.max_models != 1 || p->opt.restart_every != 0 || p->opt.learn_conflicts > 1)
+    if (p->opt.max_models != 1 || p->opt.restart_every != 0 || p->opt.learn_conflicts > 1 ||
+        p->opt.lookahead > 1)
         return fail(ASP_E_INVALID, "state import is for the plain search (one answer set, "
                                    "no restarts)");
     const int32_t V = p->hp.V, W = p->opt.W, A = p->hp.A, Rh = p->hp.Rh;
@@ -1230,7 +1267,8 @@ int32_t asp_batch_create(int32_t n, asp_program* const* progs, const asp_schedul
             o.learned_cap_lits != b->opt.learned_cap_lits || o.decision != b->opt.decision ||
             o.fallback_after != b->opt.fallback_after || o.learning != b->opt.learning ||
             o.max_models != b->opt.max_models || o.restart_every != b->opt.restart_every ||
-            std::max(o.learn_conflicts, 1) != std::max(b->opt.learn_conflicts, 1))
+            std::max(o.learn_conflicts, 1) != std::max(b->opt.learn_conflicts, 1) ||
+            (o.lookahead > 1 ? o.lookahead : 0) != (b->opt.lookahead > 1 ? b->opt.lookahead : 0))
             return fail(ASP_E_INVALID, "batch programs must share their options");
         b->progs.push_back(&progs[i]->hp);
     }
@@ -1476,6 +1514,78 @@ int32_t asp_batch_results(asp_batch* b, void* stream, int32_t* verdicts, uint8_t
     HIPCHK(hipStreamSynchronize(s));
     if (stats)
         for (int32_t i = 0; i < P.n; ++i) to_stats(ds[i], &stats[i]);
+    return ASP_OK;
+}
+
+int32_t asp_batch_learned(asp_batch* b, int32_t i, int32_t* off, int64_t cap_ng, int32_t* lits,
+                          int64_t cap_lits, int32_t* n_learned, int64_t* n_lits, void* stream) {
+    if (!b || !b->bound) return fail(ASP_E_STATE, "batch not bound");
+    if (i < 0 || i >= b->plan.n) return fail(ASP_E_INVALID, "instance index out of range");
+    hipStream_t s = (hipStream_t)stream;
+    const HostProgram& h = *b->progs[i];
+    const SlotLayout L = slot_layout(h.V, h.Rh, b->plan.W, b->plan.cap_ng, b->plan.cap_lits,
+                                     b->plan.learning);
+    uint8_t* slot = b->arena + b->plan.off_slots + b->plan.slot_off[i];
+    SlotCtrl k;
+    HIPCHK(hipMemcpyAsync(&k, slot + L.ctrl, sizeof(k), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (n_learned) *n_learned = k.n_learned;
+    if (n_lits) *n_lits = k.learned_lits;
+    if (off && k.n_learned + 1 <= cap_ng)
+        HIPCHK(hipMemcpyAsync(off, slot + L.l_off, 4 * ((size_t)k.n_learned + 1),
+                              hipMemcpyDeviceToHost, s));
+    if (lits && k.learned_lits > 0 && k.learned_lits <= cap_lits)
+        HIPCHK(hipMemcpyAsync(lits, slot + L.l_lits, 4 * (size_t)k.learned_lits,
+                              hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ASP_OK;
+}
+
+int32_t asp_scorer_train_workspace(int32_t n, asp_program* const* progs, uint64_t* bytes) {
+    if (n < 1 || !progs || !bytes) return fail(ASP_E_INVALID, "empty program list or null output");
+    std::vector<const HostProgram*> hp;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!progs[i]) return fail(ASP_E_INVALID, "null program");
+        hp.push_back(&progs[i]->hp);
+    }
+    return train_workspace(hp, bytes);
+}
+
+int32_t asp_scorer_train(int32_t n, asp_program* const* progs, const float* labels, float* params,
+                         int32_t steps, float lr, void* ws, uint64_t ws_bytes, float* loss_out,
+                         float* grad_out, void* stream) {
+    if (n < 1 || !progs || !labels || !params || !ws)
+        return fail(ASP_E_INVALID, "null argument or empty program list");
+    if ((uintptr_t)ws % kAlign) return fail(ASP_E_INVALID, "workspace must be 256-byte aligned");
+    if (steps < 0 || steps > 100000 || !(lr >= 0.f) || lr > 1.f)
+        return fail(ASP_E_INVALID, "steps must be in 0..100000 and lr in [0, 1]");
+    if (steps == 0 && !loss_out) return fail(ASP_E_INVALID, "a gradient pass needs loss_out");
+    if (train_nparam() != ASP_SCORER_NPARAM) return fail(ASP_E_INTERNAL, "parameter layout");
+    std::vector<const HostProgram*> hp;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!progs[i]) return fail(ASP_E_INVALID, "null program");
+        hp.push_back(&progs[i]->hp);
+    }
+    for (int64_t i = 0; i < ASP_SCORER_NPARAM; ++i)
+        if (!std::isfinite(params[i])) return fail(ASP_E_INVALID, "non-finite parameter");
+    std::string err;
+    int32_t rc = train_run(hp, labels, params, steps, lr, (uint8_t*)ws, ws_bytes, loss_out,
+                           grad_out, (hipStream_t)stream, &err);
+    if (rc) return fail(rc, err);
+    return ASP_OK;
+}
+
+int32_t asp_scorer_quantize(const float* params, asp_scorer_weights* w) {
+    if (!params || !w) return fail(ASP_E_INVALID, "null argument");
+    for (int64_t i = 0; i < ASP_SCORER_NPARAM; ++i)
+        if (!std::isfinite(params[i])) return fail(ASP_E_INVALID, "non-finite parameter");
+    train_quantize(params, w);
+    return ASP_OK;
+}
+
+int32_t asp_scorer_dequantize(const asp_scorer_weights* w, float* params) {
+    if (!params || !w) return fail(ASP_E_INVALID, "null argument");
+    train_dequantize(w, params);
     return ASP_OK;
 }
 

@@ -69,7 +69,8 @@ struct SlotCtrl {
 struct SlotLayout {
     int64_t ctrl;       // SlotCtrl
     int64_t val8;       // int8[V+1]
-    int64_t lvl;        // int32[V+1]
+    int64_t lvl;        // int32[V+1] (Res-learning only: the Fwd search derives
+                        // a level from the trail position and tlim)
     int64_t deps;       // uint64[(V+1)*W]
     int64_t win;        // uint64[V+1] winner key: (id*2 + pol) << 32 | map entry
     int64_t trail;      // int32[V+1]
@@ -193,6 +194,8 @@ struct KArgs {
     int64_t max_models;          // answer sets asked for; 0 all, 1 the plain search
     int64_t restart_every;       // conflicts between restarts; 0 never
     int64_t model_store;         // answer sets kept per instance (n_atoms bytes each)
+    int32_t lookahead;           // Decision candidates tried by propagation (<= 1: off)
+    int32_t pad1;
 };
 
 }  // namespace asp

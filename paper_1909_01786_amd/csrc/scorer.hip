@@ -14,7 +14,7 @@
 // nogoods), one workgroup of four waves per tile, tiles taken grid-stride so
 // each workgroup stages the layer's weights into LDS once.  A tile's edges
 // are taken 64 at a time: their source rows are gathered into an LDS operand
-// tile, multiplied by both sign matrices on the matrix cores (32x32x8 bf16
+// tile, multiplied by both sign matrices on the matrix cores (32x32x16 bf16
 // blocks, two per wave), and each product row is added into its owner's
 // int64 accumulator when its sign matches.  The epilogue multiplies the
 // tile's own rows by the self matrix, adds the normalised edge sum and the
@@ -35,9 +35,9 @@ constexpr int H = ASP_SCORER_H;   // hidden width
 constexpr int F = ASP_SCORER_F;   // input features
 constexpr int TR = 64;            // rows per tile
 constexpr int NT = 256;           // threads per workgroup
-constexpr int LD = H + 4;         // LDS row stride of bf16 operand tiles
+constexpr int LD = H + 8;         // LDS row stride of bf16 operand tiles (16-byte rows)
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 DEV const uint16_t* wmat(const ScorerArgs& a, size_t off) { return (const uint16_t*)(a.w + off); }
@@ -58,17 +58,19 @@ DEV long long norm_sum(long long s, int n) {
 }
 
 // One 32x32 block: 32 rows of an operand tile (stride LD) times 32 output
-// columns given as rows of a transposed weight tile (stride LD), K = 64.
+// columns given as rows of a transposed weight tile (stride LD), K = 64, in
+// four 32x32x16 steps; lane l supplies row / column l % 32 and k = 8 (l / 32)
+// + 0..7 of each step.
 DEV v16f mma_block(const uint16_t* A, const uint16_t* BT, int lane) {
     v16f acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    const int i = lane & 31, kh = (lane >> 5) * 4;
+    const int i = lane & 31, kh = (lane >> 5) * 8;
 #pragma unroll
-    for (int k0 = 0; k0 < H; k0 += 8) {
-        const v4s x = *(const v4s*)(A + i * LD + k0 + kh);
-        const v4s y = *(const v4s*)(BT + i * LD + k0 + kh);
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(x, y, acc, 0, 0, 0);
+    for (int k0 = 0; k0 < H; k0 += 16) {
+        const v8bf x = *(const v8bf*)(A + i * LD + k0 + kh);
+        const v8bf y = *(const v8bf*)(BT + i * LD + k0 + kh);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc, 0, 0, 0);
     }
     return acc;
 }
@@ -244,8 +246,8 @@ __global__ __launch_bounds__(NT) void k_embed(ScorerArgs a) {
 
 // Nogood update of layer l: hc = act(hc S + norm(sum hv P | hv N, |c|) + bc).
 __global__ __launch_bounds__(NT) void k_nogoods(ScorerArgs a, int l) {
-    HIP_DYNAMIC_SHARED(unsigned long long, smem);
-    const LayerLds L = carve(smem);
+    HIP_DYNAMIC_SHARED(uint4, smem16);   // 16-byte aligned base for the bf16 operand rows
+    const LayerLds L = carve((unsigned long long*)smem16);
     const int tid = threadIdx.x;
     const size_t HH = (size_t)H * H;
     stage_t(L.wt, wmat(a, offsetof(asp_scorer_weights, P)) + l * HH, tid);
@@ -298,8 +300,8 @@ __global__ __launch_bounds__(NT) void k_nogoods(ScorerArgs a, int l) {
 // Variable update of layer l: hv = act(hv T + norm(sum hc Q | hc R, deg v) + bv);
 // the last layer also writes each atom's score hv . wo + bo.
 __global__ __launch_bounds__(NT) void k_vars(ScorerArgs a, int l, int last) {
-    HIP_DYNAMIC_SHARED(unsigned long long, smem);
-    const LayerLds L = carve(smem);
+    HIP_DYNAMIC_SHARED(uint4, smem16);   // 16-byte aligned base for the bf16 operand rows
+    const LayerLds L = carve((unsigned long long*)smem16);
     __shared__ int sWo[H];
     const int tid = threadIdx.x;
     const size_t HH = (size_t)H * H;

@@ -122,6 +122,7 @@ struct Ctx {
                             // several conflicts learned per step (compile-time in k_search)
     int32_t multi;          // several conflicts learned per step (compile-time in k_search)
     int32_t learn_k;        // round conflicts learned per step
+    int32_t lookahead;      // Decision candidates tried by propagation (extended search)
     unsigned long long my_visits, my_checks;
 };
 
@@ -565,8 +566,8 @@ DEV void step_init(Ctx& c, Ctl& k) {
             int x = c.trail[i];
             uint32_t code = vget(c.pendb, x);
             vset(c.valb, x, code);
-            c.lvl[x] = 1;
             if (c.learning == LEARN_RES) {
+                c.lvl[x] = 1;
                 c.gpos[x] = q0;
                 c.reason[x] = -1;    // never resolved: conflicts at level 1 mean UNSAT
             }
@@ -904,8 +905,8 @@ DEV void step_round(Ctx& c, Ctl& k) {
             }
             if (rec) put_record(c, i - qt, x, code, dx[0]);
         }
-        c.lvl[x] = cdl;
         if (c.learning == LEARN_RES) {
+            c.lvl[x] = cdl;
             c.gpos[x] = qt;
             c.reason[x] = id;
         }
@@ -1135,7 +1136,7 @@ DEV void restart(Ctx& c, Ctl& k) {
     for (int i = tid; i < words; i += T) c.valb[i] = 0u;
     for (int i = tid; i < k.qt; i += T) {
         const int v = c.trail[i];
-        c.lvl[v] = 0;
+        if (c.learning == LEARN_RES) c.lvl[v] = 0;
         for (int w = 0; w < W; ++w) c.deps[(size_t)v * W + w] = 0ull;
     }
     for (int w = tid; w < W; w += T) c.sB[w] = 0ull;
@@ -1387,8 +1388,10 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     for (int i = start + tid; i < k.qt; i += T) {
         int v = c.trail[i];
         vclr(c.valb, v);
-        c.lvl[v] = 0;
-        for (int w = 0; w < W; ++w) c.deps[(size_t)v * W + w] = 0ull;
+        if (c.learning == LEARN_RES) {
+            c.lvl[v] = 0;
+            for (int w = 0; w < W; ++w) c.deps[(size_t)v * W + w] = 0ull;
+        }
     }
     bar();
     k.pool_top = uni(c.scr->pool_top);
@@ -1411,8 +1414,8 @@ DEV void step_learn(Ctx& c, Ctl& k, const KArgs& a) {
     const int x = lvar(top);
     for (int w = tid; w < W; w += T) c.deps[(size_t)x * W + w] = c.sB[w];
     vset(c.valb, x, top > 0 ? VF : VT);   // identical from every lane
-    c.lvl[x] = bj;
     if (c.learning == LEARN_RES) {
+        c.lvl[x] = bj;
         c.gpos[x] = start;
         c.reason[x] = newid;
     }
@@ -1444,8 +1447,9 @@ DEV void at_fixpoint(Ctl& k) {
 // its order as unsigned) << 32 | (~rule), 0 if none.  BY_ACT reads the
 // head's activity, else score[j]; four rules per lane at a time, so their
 // loads are issued together.
-template <bool BY_ACT>
-DEV unsigned long long best_rule(Ctx& c, const Ctl& k, const int32_t* score) {
+template <bool BY_ACT, bool BELOW = false>
+DEV unsigned long long best_rule(Ctx& c, const Ctl& k, const int32_t* score,
+                                 unsigned long long below = 0ull) {
     const int T = c.T, A = k.A, Rh = k.Rh;
     unsigned long long best = 0ull;
     constexpr int U = 4;
@@ -1470,10 +1474,104 @@ DEV unsigned long long best_rule(Ctx& c, const Ctl& k, const int32_t* score) {
             const unsigned long long key =
                 ((unsigned long long)((uint32_t)sc[u] ^ 0x80000000u) << 32) |
                 (unsigned long long)(0xffffffffu - (uint32_t)j);
+            if (BELOW && key >= below) continue;
             best = key > best ? key : best;
         }
     }
     return best;
+}
+
+// Assign T b_j at the next level (the decided literal; its Deps is the
+// level's bit) and make it the frontier.  Counters and trace untouched.
+DEV void decide_rule(Ctx& c, Ctl& k, int j) {
+    const int T = c.T, tid = c.tid, W = c.W;
+    const int b = k.A + 3 * j + 1;
+    const int ncdl = k.cdl + 1;
+    const int bit = level_bit(ncdl, W);
+    for (int w = tid; w < W; w += T)
+        c.deps[(size_t)b * W + w] = (w == (bit >> 6)) ? (1ull << (bit & 63)) : 0ull;
+    c.tlim[ncdl] = k.qt;                 // identical stores from every lane
+    c.dec[ncdl] = b;
+    if (c.learning == LEARN_RES) {
+        c.lvl[b] = ncdl;
+        c.gpos[b] = k.qt;
+        c.reason[b] = -1;
+    }
+    c.trail[k.qt] = b;
+    vset(c.valb, b, VT);
+    put_record(c, 0, b, VT, bit < 64 ? (1ull << bit) : 0ull);   // identical from every lane
+    bar();
+    k.cdl = ncdl;
+    k.qh = k.qt;
+    k.qt = k.qt + 1;
+    k.fr_ok = 1;
+}
+
+DEV int rule_of(unsigned long long key) { return (int)(0xffffffffu - (uint32_t)(key & 0xffffffffull)); }
+
+// Lookahead Decision (extended search, Fwd-learning): the candidates with
+// the `lookahead` best keys -- best first, `best` the first -- are tried in
+// order; a trial decides the rule and runs rounds until a fixpoint or a
+// conflict.  A trial ending in a conflict or with every variable assigned
+// stands as the Decision.  Otherwise the variables it assigned are counted
+// (trace event 10, rule, count) and it is undone: the trail is cut back and
+// the values cleared (Deps of unassigned variables are never read).  With
+// no trial standing, the candidate with the most assignments (earliest on
+// ties) is decided.
+DEV void lookahead_decide(Ctx& c, Ctl& k, unsigned long long best, const int32_t* score) {
+    const int T = c.T, tid = c.tid;
+    unsigned long long keys[8];
+    int n = 1;
+    keys[0] = best;
+    const bool by_act = c.decision == DECISION_ACTIVITY;
+    for (int i = 1; i < c.lookahead && i < 8; ++i) {
+        const unsigned long long mine = by_act ? best_rule<true, true>(c, k, c.RO, keys[i - 1])
+                                               : best_rule<false, true>(c, k, score, keys[i - 1]);
+        const unsigned long long nxt = block_max_u64(c, mine);
+        bar();
+        if (nxt == 0ull) break;
+        keys[n++] = nxt;
+    }
+    int pick = rule_of(best);
+    if (n > 1) {
+        const int consec0 = k.consec, open0 = k.dec_open, cdl0 = k.cdl, qt0 = k.qt;
+        int best_p = -1;
+        for (int i = 0; i < n; ++i) {
+            const int j = rule_of(keys[i]);
+            decide_rule(c, k, j);
+            k.dec_open = 1;
+            while (k.qt > k.qh && !k.pend_kind && k.status == ST_RUNNING) {
+                step_round(c, k);
+                bar();
+            }
+            if (k.pend_kind || k.qt == k.V || k.status != ST_RUNNING) {
+                k.decisions += 1;
+                k.hash = fnv(k.hash, 1);
+                k.hash = fnv(k.hash, j);
+                return;
+            }
+            const int p = k.qt - qt0;
+            k.hash = fnv(k.hash, 10);
+            k.hash = fnv(k.hash, j);
+            k.hash = fnv(k.hash, p);
+            for (int q = qt0 + tid; q < k.qt; q += T) vclr(c.valb, c.trail[q]);
+            bar();
+            k.qt = k.qh = qt0;
+            k.cdl = cdl0;
+            k.fr_ok = 0;
+            k.consec = consec0;
+            k.dec_open = open0;
+            if (p > best_p) {
+                best_p = p;
+                pick = j;
+            }
+        }
+    }
+    decide_rule(c, k, pick);
+    k.decisions += 1;
+    k.dec_open = 1;
+    k.hash = fnv(k.hash, 1);
+    k.hash = fnv(k.hash, pick);
 }
 
 DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
@@ -1482,34 +1580,20 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
     // key: head score (signed, biased to keep its order) then lowest rule;
     // the score is the static per-rule table (occurrences or Jeroslow-Wang),
     // the supplied scores, or the head's activity
+    const int32_t* score = k.use_score ? c.RS : c.RO;
     const unsigned long long mine = c.ext && c.decision == DECISION_ACTIVITY
                                         ? best_rule<true>(c, k, c.RO)
-                                        : best_rule<false>(c, k, k.use_score ? c.RS : c.RO);
+                                        : best_rule<false>(c, k, score);
     unsigned long long best = mine;
     best = block_max_u64(c, best);
     bar();
     if (best != 0ull) {
-        const int j = (int)(0xffffffffu - (uint32_t)(best & 0xffffffffull));
-        const int b = A + 3 * j + 1;
-        const int ncdl = k.cdl + 1;
-        const int bit = level_bit(ncdl, W);
-        for (int w = tid; w < W; w += T)
-            c.deps[(size_t)b * W + w] = (w == (bit >> 6)) ? (1ull << (bit & 63)) : 0ull;
-        c.tlim[ncdl] = k.qt;                 // identical stores from every lane
-        c.dec[ncdl] = b;
-        c.lvl[b] = ncdl;
-        if (c.learning == LEARN_RES) {
-            c.gpos[b] = k.qt;
-            c.reason[b] = -1;
+        if (c.ext && c.lookahead > 1) {
+            lookahead_decide(c, k, best, score);
+            return STEP_DECIDE;
         }
-        c.trail[k.qt] = b;
-        vset(c.valb, b, VT);
-        put_record(c, 0, b, VT, bit < 64 ? (1ull << bit) : 0ull);   // identical from every lane
-        bar();
-        k.cdl = ncdl;
-        k.qh = k.qt;
-        k.qt = k.qt + 1;
-        k.fr_ok = 1;
+        const int j = rule_of(best);
+        decide_rule(c, k, j);
         k.decisions += 1;
         k.dec_open = 1;
         k.hash = fnv(k.hash, 1);
@@ -1523,8 +1607,8 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
     for (int p = 1 + tid; p <= A; p += T) {
         if (vget(c.valb, p) != 0u) continue;
         for (int w = 0; w < W; ++w) c.deps[(size_t)p * W + w] = alldec_word(w, cdl, W);
-        c.lvl[p] = cdl;
         if (c.learning == LEARN_RES) {
+            c.lvl[p] = cdl;
             c.gpos[p] = k.qt;
             c.reason[p] = -1;
         }
@@ -1798,6 +1882,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void 
     c.ext = EN >= 1;
     c.multi = EN == 2;
     c.learn_k = a.learn_k;
+    c.lookahead = a.lookahead;
     c.T = MAXT;
     c.tid = threadIdx.x;
     c.lane = threadIdx.x & 63;
@@ -1879,7 +1964,8 @@ static hipError_t launch_v(const KArgs& a, int threads, int grid, size_t lds, hi
 
 static int search_mode(const KArgs& a) {
     if (a.learn_k > 1) return 2;
-    return (a.max_models != 1 || a.restart_every != 0 || a.decision == DECISION_ACTIVITY) ? 1 : 0;
+    return (a.max_models != 1 || a.restart_every != 0 || a.decision == DECISION_ACTIVITY ||
+            a.lookahead > 1) ? 1 : 0;
 }
 
 template <int LR>

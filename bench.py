@@ -555,6 +555,11 @@ def main():
         "launch_ms": [c[3] for c in info],
         "instance_ms": tl,
         "time_split": {"all": split_all, "dominant_launch": split_dom},
+        "per_class": [{"instances": c[1], "threads": c[2], "launch_ms": c[3],
+                       "instance_ms": tail([stats[int(i)] for i in order[c[0]:c[0] + c[1]]]),
+                       "us_per_round": time_split(stats, [int(i) for i in order[c[0]:c[0] + c[1]]])["us_per_round"],
+                       "rounds_per_instance": time_split(stats, [int(i) for i in order[c[0]:c[0] + c[1]]])["rounds_per_instance"]}
+                      for c in info],
         "counters": search_counters(stats, ms_step),
         "host_encode_s": t_enc, "bind_s": t_bind,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -432,7 +432,8 @@ class Program:
         array (no arena; the program need not be bound)."""
         m = np.zeros(max(self.n_atoms, 1), np.uint8)
         s = asp_stats()
-        st = _check(lib().asp_solve_noalloc(self._h, _stream_ptr(stream),
+        sp = _stream_ptr(stream) if stream is not None else None   # None: the default stream
+        st = _check(lib().asp_solve_noalloc(self._h, sp,
                                             C.byref(lim) if lim else None, _ptr(m), C.byref(s)))
         return st, (m[:self.n_atoms].copy() if st == SAT else None), s.as_dict()
 

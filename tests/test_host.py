@@ -77,6 +77,30 @@ def test_invalid_inputs(P):
         P.Program(aspgen.from_rules(2, [(1, [2])]), W=65)
 
 
+def test_host_side_argument_checks(P):
+    """Refusals that happen before any device call: the allocation-free
+    solve's size limit and score mode, training arguments, options."""
+    from paper_1909_01786_amd.binding import AspError, NOALLOC_MAX_BYTES, SCORER_NPARAM
+    import paper_1909_01786_amd.binding as B
+    g = P.Program(aspgen.single_random(1001))        # default learned-store capacities
+    assert g.sizes.device_bytes > NOALLOC_MAX_BYTES
+    with pytest.raises(AspError) as e:
+        g.solve_noalloc(P.limits(10, 1000))
+    assert e.value.status == -2
+    with pytest.raises(AspError) as e:
+        P.Program(aspgen.tiny_program(1), decision=P.DECISION_SCORE).solve_noalloc()
+    assert e.value.status == -1
+    for kw in (dict(lookahead=9), dict(lookahead=2, learning=P.LEARN_RES)):
+        with pytest.raises(AspError):
+            P.Program(aspgen.tiny_program(1), **kw)
+    bad = np.zeros(SCORER_NPARAM, np.float32)
+    bad[5] = np.nan
+    with pytest.raises(AspError):
+        B.quantize(bad)
+    with pytest.raises(ValueError):
+        B.quantize(np.zeros(10, np.float32))
+
+
 def test_status_strings(P):
     from paper_1909_01786_amd.binding import asp_status_str
     assert asp_status_str(1) == "sat" and asp_status_str(-2) == "capacity exceeded"

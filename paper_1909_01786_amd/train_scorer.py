@@ -38,9 +38,10 @@ import aspgen  # noqa: E402
 from paper_1909_01786_amd import binding as B  # noqa: E402
 
 
-def trace_labels(prog, verdict, model, learned_lits, q):
+def trace_labels(prog, verdict, model, learned_lits, q, sat_only=False):
     """Per-atom labels of one training program from its trace (see the
-    module docstring); float32 over atoms 1..A, -1 = no label."""
+    module docstring); float32 over atoms 1..A, -1 = no label.  sat_only:
+    programs without an answer set get no labels."""
     A = int(prog.n_atoms)
     head = np.asarray(prog.head)
     heads = head[head != 0]                     # headed rule j -> its head
@@ -49,6 +50,8 @@ def trace_labels(prog, verdict, model, learned_lits, q):
     has_rule[heads] = True
     if verdict == B.SAT:
         lab[has_rule[1:]] = model[has_rule[1:]].astype(np.float32)
+        return lab, 0
+    if sat_only:
         return lab, 0
     lits = np.asarray(learned_lits, np.int64)
     b = lits[lits > A]                          # decision literals T b_r
@@ -78,6 +81,8 @@ def main(argv=None) -> int:
     ap.add_argument("--init-spread", type=int, default=24)
     ap.add_argument("--budget", type=int, default=2000)
     ap.add_argument("--quantile", type=float, default=0.8)
+    ap.add_argument("--sat-only", action="store_true",
+                    help="label only programs with an answer set (answer-set atoms)")
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--out", default=B.WEIGHTS_PATH)
@@ -100,7 +105,7 @@ def main(argv=None) -> int:
     labels, n_dec_lits = [], 0
     for i, p in enumerate(progs):
         _, lits = b.learned(i)
-        lab, nd = trace_labels(p, int(verd[i]), models[i], lits, args.quantile)
+        lab, nd = trace_labels(p, int(verd[i]), models[i], lits, args.quantile, args.sat_only)
         labels.append(lab)
         n_dec_lits += nd
     n_conf = int(sum(int(s["conflicts"]) for s in stats))
@@ -121,7 +126,8 @@ def main(argv=None) -> int:
     w = B.quantize(params)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     meta = {"train_seed": args.seed, "n_random": args.n_random, "n_hc": args.n_hc,
-            "budget": args.budget, "quantile": args.quantile, "steps": args.steps,
+            "budget": args.budget, "quantile": args.quantile, "sat_only": args.sat_only,
+            "steps": args.steps,
             "lr": args.lr, "init_seed": args.init_seed, "init_spread": args.init_spread,
             "decisions": n_dec, "conflicts": n_conf, "labelled_atoms": n_lab,
             "positive_rate": float((lab_all == 1).sum() / max(n_lab, 1)),

@@ -175,7 +175,9 @@ int encode_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
             for (int32_t k = b; k < e; ++k) {
                 MapEntry m{(int32_t)id, P->ng_lits[k], 0, 0, 0, 0, 0, 0};
                 if (e - b > 3) {
-                    m.o1 = kLongNogood;
+                    m.o1 = kLongNogood;   // the nogood's literals: ng_lits[o2 .. o2 + a1)
+                    m.o2 = b;
+                    m.a1 = e - b;
                 } else {
                     int32_t* o = &m.o1;
                     int32_t* seg = &m.a1;

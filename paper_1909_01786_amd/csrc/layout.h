@@ -22,8 +22,9 @@ constexpr int kAlign = 256;
 // literal, and the nogood's other literals when it has at most three (0
 // pads the unused ones), each with the map segment (start, size) of its
 // complement -- the literal a unit nogood makes true.  A longer nogood has
-// o1 = kLongNogood and is read from the nogood CSR.  A visit of a short
-// nogood is one 32-byte load.
+// o1 = kLongNogood, o2 = the start of its literals in the nogood CSR and
+// a1 = their count, so that its literals are read right after the entry.
+// A visit of a short nogood is one 32-byte load.
 struct alignas(32) MapEntry {
     int32_t id, self, o1, o2;
     int32_t a1, n1, a2, n2;

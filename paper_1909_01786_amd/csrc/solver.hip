@@ -54,6 +54,7 @@ constexpr int kWinCap = 1 << kWinBits;   // LDS winner table (variables implied 
 constexpr int kWinProbe = 32;
 constexpr int kImplCap = 128;    // LDS implication slots (Deps candidate and record)
 constexpr uint32_t SLOT_TAG = 0x80000000u;
+constexpr int kLitBatch = 4;     // literals of a long nogood loaded together in a visit
 
 // Uniform search state: identical in every lane.
 struct Ctl {
@@ -164,14 +165,21 @@ DEV uint64_t fnv(uint64_t h, int32_t w) {
     return h;
 }
 
-DEV int wave_incl_scan(int x, int lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
+// Inclusive prefix sum over the 64 lanes of a wave (every lane active), by
+// data-parallel-primitive moves: shifts by 1, 2, 4 and 8 lanes inside each
+// row of 16 (lanes shifted in from outside the row add 0), then lane 15 of
+// rows 0 and 2 added to rows 1 and 3, then lane 31 added to rows 2 and 3.
+// Each step is a VALU move, not an LDS round trip.
+DEV int wave_incl_scan(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
     return x;
 }
+DEV int wave_last(int x) { return __builtin_amdgcn_readlane(x, 63); }
 
 // Block-wide reductions; every lane must call them.
 DEV unsigned long long block_max_u64(Ctx& c, unsigned long long x) {
@@ -631,21 +639,27 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
         }
     } else {
         eidx = NO_ENTRY;
-        ng_span(c, k, id, lits, len);
+        if (id < k.nS) {
+            // a long static nogood: its map entry locates its literals
+            lits = c.NL + e.o2;
+            len = e.a1;
+        } else {
+            ng_span(c, k, id, lits, len);
+        }
         if (pass == 0) {
             c.my_visits += 1ull;
             c.my_checks += (unsigned long long)len;
         }
-        // from the last literal back, four loads in flight: a learned
+        // from the last literal back, kLitBatch loads in flight: a learned
         // nogood holds its newest literal last, the one most likely to be
         // open or false after a backjump (the outcome -- violated, unit on
         // one literal, or neither -- does not depend on the order)
-        for (int q = len; q > 0; q -= 4) {
-            int l[4];
+        for (int q = len; q > 0; q -= kLitBatch) {
+            int l[kLitBatch];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) l[j] = j < q ? lits[q - 1 - j] : 0;
+            for (int j = 0; j < kLitBatch; ++j) l[j] = j < q ? lits[q - 1 - j] : 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < kLitBatch; ++j) {
                 if (j >= q) break;
                 const uint32_t s = vget(c.valb, lvar(l[j]));
                 if (s == 0u) {
@@ -767,13 +781,13 @@ DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
         // wave-local exclusive offsets of the visit counts, and the wave
         // totals: one barrier makes every visit's position known
         const int cnt_all = cs + cl;
-        const int inc = wave_incl_scan(cnt_all, c.lane);
+        const int inc = wave_incl_scan(cnt_all);
         c.sOff[tid] = inc - cnt_all;
         c.sS0[tid] = s0;
         c.sCs[tid] = cs;
         c.sL0[tid] = l0;
         c.sDeps[tid] = sd;
-        c.scr->wsum[c.wid] = __shfl(inc, 63, 64);   // identical from the wave's lanes
+        c.scr->wsum[c.wid] = wave_last(inc);   // identical from the wave's lanes
         bar();
         const int nf = (qt - base) < T ? (qt - base) : T;
         const int nwv = (nf + 63) >> 6;
@@ -787,12 +801,19 @@ DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
                 wb += c.scr->wsum[w];
                 ++w;
             }
+            // the last of the wave's 64 start offsets that is <= qq (they
+            // ascend; lanes past the frontier hold the wave total, > qq):
+            // count the offsets <= qq among every eighth, then among the
+            // eight of that group -- two rounds of independent LDS reads
             const int qq = q - wb;
-            int lo = w * 64, hi = min(nf, w * 64 + 64) - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (c.sOff[mid] <= qq) lo = mid; else hi = mid - 1;
-            }
+            const int32_t* so = c.sOff + w * 64;
+            int g = 0;
+#pragma unroll
+            for (int m = 1; m < 8; ++m) g += so[8 * m] <= qq ? 1 : 0;
+            int r = 0;
+#pragma unroll
+            for (int m = 1; m < 8; ++m) r += so[8 * g + m] <= qq ? 1 : 0;
+            const int lo = w * 64 + 8 * g + r;
             const int j = qq - c.sOff[lo];
             const int cnt = c.sCs[lo];
             if (j < cnt) {
@@ -1666,8 +1687,8 @@ DEV void answer_set(Ctx& c, Ctl& k, const KArgs& a) {
     for (int b0 = 1; b0 <= A; b0 += T) {
         const int p = b0 + tid;
         const int f = (p <= A && vget(c.valb, p) == VT) ? 1 : 0;
-        const int inc = wave_incl_scan(f, c.lane);
-        c.scr->wsum[c.wid] = __shfl(inc, 63, 64);   // identical from the wave's lanes
+        const int inc = wave_incl_scan(f);
+        c.scr->wsum[c.wid] = wave_last(inc);   // identical from the wave's lanes
         bar();
         int off = 0, tot = 0;
         for (int w = 0; w < c.nw; ++w) {

@@ -24,7 +24,7 @@
 #include "train.h"
 
 namespace asp {
-size_t lds_bytes(int threads, int words);
+size_t lds_bytes(int threads, int words, int awords);
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s);
 hipError_t set_max_lds(int threads, size_t lds);
 }  // namespace asp
@@ -82,7 +82,7 @@ bool valid_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 |
 // One launch of the search kernel: instances order[first .. first+count),
 // LDS sized for the largest of them.
 struct LaunchClass {
-    int32_t first = 0, count = 0, words = 1, threads = 128;
+    int32_t first = 0, count = 0, words = 1, awords = 1, threads = 128;
     size_t lds = 0;
 };
 
@@ -265,13 +265,18 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
         LaunchClass lc;
         lc.first = k;
         const int c = cls(P.order[k]);
-        int64_t vmax = 0;
-        while (k < P.n && cls(P.order[k]) == c) vmax = std::max<int64_t>(vmax, progs[P.order[k++]]->V);
+        int64_t vmax = 0, amax = 0;
+        while (k < P.n && cls(P.order[k]) == c) {
+            vmax = std::max<int64_t>(vmax, progs[P.order[k]]->V);
+            amax = std::max<int64_t>(amax, progs[P.order[k]]->A);
+            ++k;
+        }
         lc.count = k - lc.first;
         lc.words = (int32_t)((vmax + 1 + 15) / 16);
+        lc.awords = (int32_t)((amax + 1 + 31) / 32);
         const int ci = (int)P.classes.size();
         lc.threads = (class_threads && ci < 4 && class_threads[ci] > 0) ? class_threads[ci] : threads;
-        lc.lds = lds_bytes(lc.threads, lc.words);
+        lc.lds = lds_bytes(lc.threads, lc.words, lc.awords);
         P.classes.push_back(lc);
     }
     uint64_t o = 0;
@@ -377,6 +382,7 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& 
     a.model_store = P.model_store;
     a.lookahead = P.lookahead;
     a.words = lc.words;
+    a.awords = lc.awords;
     a.step_mask = 0;
     a.max_steps = -1;
     a.max_conflicts = -1;

@@ -70,6 +70,8 @@ struct SlotCtrl {
 struct SlotLayout {
     int64_t ctrl;       // SlotCtrl
     int64_t val8;       // int8[V+1]
+    int64_t pend;       // uint32[(V+1+15)/16] values implied in the current round for
+                        // variables past the LDS winner table (2 bits each); zero at rest
     int64_t lvl;        // int32[V+1] (Res-learning only: the Fwd search derives
                         // a level from the trail position and tlim)
     int64_t deps;       // uint64[(V+1)*W]
@@ -105,6 +107,7 @@ __host__ __device__ inline SlotLayout slot_layout(int64_t V, int64_t Rh, int32_t
 #define ASP_TAKE(field, bytes) do { L.field = o; o = (o + (bytes) + kAlign - 1) / kAlign * kAlign; } while (0)
     ASP_TAKE(ctrl, (int64_t)sizeof(SlotCtrl));
     ASP_TAKE(val8, V1);
+    ASP_TAKE(pend, 4 * ((V1 + 15) / 16));
     ASP_TAKE(lvl, 4 * V1);
     ASP_TAKE(deps, 8 * V1 * W);
     ASP_TAKE(win, 8 * V1);
@@ -196,7 +199,7 @@ struct KArgs {
     int64_t restart_every;       // conflicts between restarts; 0 never
     int64_t model_store;         // answer sets kept per instance (n_atoms bytes each)
     int32_t lookahead;           // Decision candidates tried by propagation (<= 1: off)
-    int32_t pad1;
+    int32_t awords;              // LDS words of the 1-bit atom map (this launch's largest A)
 };
 
 }  // namespace asp

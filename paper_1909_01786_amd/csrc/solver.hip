@@ -8,15 +8,17 @@
 // instance; instances are launched by LDS size class, largest first.
 //
 // Data placement:
-//  * LDS: the assignment as 2 bits per variable (1 = true, 2 = false) and a
-//    second 2-bit map of the values implied in the current round; scan
-//    buffers that spread a round's (literal, nogood) visits over the lanes.
+//  * LDS: the assignment as 2 bits per variable (1 = true, 2 = false); the
+//    round's winner table (implied variable -> lowest implier, and the values
+//    implied for it); scan buffers that spread a round's (literal, nogood)
+//    visits over the lanes; a 1-bit atom map for the stability check.
 //  * HBM (read-only, per instance): nogood CSR, literal->nogood map CSR,
 //    rule table.  Visits read a map segment and then the nogood's literals.
 //  * HBM (per instance slot): levels, Deps bitmaps (W x 64 bit per
 //    variable), the trail (assigned variables in order, whose tail is the
-//    round frontier), the lowest-id implier per variable, the learned
-//    nogoods and their literal occurrence lists.
+//    round frontier), the lowest-id implier and the implied values of the
+//    variables that do not fit the LDS table, the learned nogoods and their
+//    literal occurrence lists.
 //
 // Control discipline: the search state (decision level, trail pointers, counters,
 // status) is a struct that every lane of every wave holds and updates
@@ -98,8 +100,9 @@ struct Ctx {
     unsigned long long* win;
     uint64_t* deps;
     int64_t pool_cap;
+    uint32_t* pendb;        // 2-bit pending map past the LDS table (workgroup atomics)
     // LDS
-    uint32_t *valb, *pendb;
+    uint32_t *valb, *lm;
     int32_t *sOff, *sS0, *sCs, *sL0;
     // frontier records: map segment (start, size) and learned occurrence
     // list (start, size) of each frontier variable's true literal, and the
@@ -109,7 +112,7 @@ struct Ctx {
     // implication slots (W = 1): the Deps of an implier's other variables
     // and the record of the literal it makes true, computed at visit time so
     // that applying the winner reads LDS only
-    int32_t* tKey;
+    int32_t *tKey, *tCode;
     unsigned long long *tWin, *iDeps;
     // Deps word of each frontier variable (W = 1), per record and per lane
     // of the visit pass
@@ -139,6 +142,25 @@ DEV int64_t uni64(int64_t x) {
 DEV uint32_t vget(const uint32_t* b, int v) { return (b[v >> 4] >> ((v & 15) << 1)) & 3u; }
 DEV void vset(uint32_t* b, int v, uint32_t code) { atomicOr(&b[v >> 4], code << ((v & 15) << 1)); }
 DEV void vclr(uint32_t* b, int v) { atomicAnd(&b[v >> 4], ~(3u << ((v & 15) << 1))); }
+// The pending map lives in the slot (global memory), shared inside the
+// workgroup only: workgroup-scope atomics, ordered by the barriers.
+DEV uint32_t pend_or(uint32_t* b, int v, uint32_t code) {
+    const uint32_t sh = (uint32_t)(v & 15) << 1;
+    const uint32_t old = __hip_atomic_fetch_or(&b[v >> 4], code << sh, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    return (old >> sh) & 3u;
+}
+DEV uint32_t pend_get(uint32_t* b, int v) {
+    return (__hip_atomic_load(&b[v >> 4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >>
+            ((v & 15) << 1)) & 3u;
+}
+DEV void pend_clr(uint32_t* b, int v) {
+    __hip_atomic_fetch_and(&b[v >> 4], ~(3u << ((v & 15) << 1)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+DEV void pend_zero(uint32_t* b, int i) {
+    __hip_atomic_store(&b[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 DEV uint32_t lcode(int l) { return l > 0 ? VT : VF; }     // value making literal l true
 DEV int lvar(int l) { return l < 0 ? -l : l; }
 DEV int lidx(int l) { return 2 * lvar(l) + (l < 0 ? 1 : 0); }
@@ -293,13 +315,18 @@ DEV unsigned long long alldec_word(int w, int cdl, int W) {
 
 DEV int tab_hash(int x) { return (int)(((uint32_t)x * 0x9E3779B1u) >> (32 - kWinBits)); }
 
-// Slot of variable x in the round's winner table (inserted if absent);
-// -1 when the probe window is full (the global table is used instead).
-DEV int tab_insert(Ctx& c, int x) {
+// Slot of variable x in the round's winner table (inserted if absent;
+// `first` is set for the one lane that inserted it); -1 when the probe
+// window is full (the global table is used instead).  For a given x every
+// lane gets the same answer: entries are never removed during a round, so
+// a lane probing for x passes the same occupied slots as the lane that
+// inserted it, and a full window stays full.
+DEV int tab_insert(Ctx& c, int x, int& first) {
     const int h = tab_hash(x);
     for (int p = 0; p < kWinProbe; ++p) {
         const int sl = (h + p) & (kWinCap - 1);
         const int old = atomicCAS(&c.tKey[sl], -1, x);
+        if (old == -1) first = 1;
         if (old == -1 || old == x) return sl;
     }
     return -1;
@@ -320,6 +347,7 @@ DEV int tab_find(const Ctx& c, int x) {
 DEV void tab_clear_all(Ctx& c) {
     for (int i = c.tid; i < kWinCap; i += c.T) {
         c.tKey[i] = -1;
+        c.tCode[i] = 0;
         c.tWin[i] = WIN_NONE;
     }
 }
@@ -348,6 +376,7 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     c.RBL = a.rb_lits + d.rb_lits;
     c.ctrl = (SlotCtrl*)(slot + lay.ctrl);
     c.val8 = (int8_t*)(slot + lay.val8);
+    c.pendb = (uint32_t*)(slot + lay.pend);
     c.lvl = (int32_t*)(slot + lay.lvl);
     c.deps = (uint64_t*)(slot + lay.deps);
     c.win = (unsigned long long*)(slot + lay.win);
@@ -374,8 +403,9 @@ DEV void reset_search(Ctx& c, Ctl& k) {
     const int words = (V + 1 + 15) >> 4;
     for (int i = tid; i < words; i += T) {
         c.valb[i] = 0u;
-        c.pendb[i] = 0u;
+        pend_zero(c.pendb, i);
     }
+    for (int i = tid; i < ((k.A + 1 + 31) >> 5); i += T) c.lm[i] = 0u;
     for (int v = tid; v <= V; v += T) {
         c.lvl[v] = 0;
         c.val8[v] = 0;
@@ -424,7 +454,8 @@ DEV void reset_search(Ctx& c, Ctl& k) {
 DEV void load_ctrl(Ctx& c, Ctl& k) {
     const int V = k.V, T = c.T, tid = c.tid;
     const int words = (V + 1 + 15) >> 4;
-    for (int i = tid; i < words; i += T) c.pendb[i] = 0u;
+    for (int i = tid; i < words; i += T) pend_zero(c.pendb, i);
+    for (int i = tid; i < ((k.A + 1 + 31) >> 5); i += T) c.lm[i] = 0u;
     for (int i = tid; i < words; i += T) {
         uint32_t wv = 0;
         for (int q = 0; q < 16; ++q) {
@@ -554,9 +585,7 @@ DEV void step_init(Ctx& c, Ctl& k) {
             }
             int x = lvar(l);
             uint32_t code = l > 0 ? VF : VT;
-            uint32_t sh = (uint32_t)(x & 15) << 1;
-            uint32_t old = atomicOr(&c.pendb[x >> 4], code << sh);
-            uint32_t ob = (old >> sh) & 3u;
+            const uint32_t ob = pend_or(c.pendb, x, code);
             if (ob == 0u) {
                 int pos = atomicAdd(&c.scr->tail, 1);
                 c.trail[pos] = x;
@@ -572,7 +601,7 @@ DEV void step_init(Ctx& c, Ctl& k) {
     if (!clash) {
         for (int i = q0 + tid; i < q1; i += T) {
             int x = c.trail[i];
-            uint32_t code = vget(c.pendb, x);
+            uint32_t code = pend_get(c.pendb, x);
             vset(c.valb, x, code);
             if (c.learning == LEARN_RES) {
                 c.lvl[x] = 1;
@@ -582,7 +611,7 @@ DEV void step_init(Ctx& c, Ctl& k) {
         }
     }
     bar();
-    for (int i = q0 + tid; i < q1; i += T) vclr(c.pendb, c.trail[i]);
+    for (int i = q0 + tid; i < q1; i += T) pend_clr(c.pendb, c.trail[i]);
     bar();
     k.init_done = 1;
     if (clash) {
@@ -686,62 +715,76 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
     if (pass == 0) {
         const uint32_t hi = (uint32_t)(id * 2 + (code == VF ? 1 : 0));
         uint32_t lo = eidx;
+        // W = 1: the Deps this implication would give x (the snapshot's Deps
+        // of the nogood's other variables) and the record of the literal it
+        // makes true, kept in a slot in case this implier wins (the map
+        // literal's variable is the frontier variable: its Deps come with
+        // the frontier; a short nogood's entry holds the map segment of each
+        // literal it can make true; under Fwd-learning learned occurrence
+        // lists exist only for decision literals T b_r -- and, when answer
+        // sets are blocked, atoms T p -- under Res-learning for literals of
+        // either sign).  Their global reads are issued first; the LDS
+        // atomics that follow (x's winner-table entry, the slot) overlap them.
+        unsigned long long dA = 0ull, dB = 0ull;
+        int s0 = 0, s1 = 0, l0 = 0, cl = 0;
+        const bool dec_lit = c.learning == LEARN_RES || (c.ext && code == VT) ||
+                             (code == VT && x > k.A && (x - k.A - 1) % 3 == 0);
         if (c.W == 1) {
-            // the Deps this implication would give x (the snapshot's Deps of
-            // the nogood's other variables) and the record of the literal it
-            // makes true, kept in a slot in case this implier wins
-            // (the map literal's variable is the frontier variable: its Deps
-            // come with the frontier; a short nogood's entry holds the map
-            // segment of each literal it can make true; under Fwd-learning
-            // learned occurrence lists exist only for decision literals T b_r
-            // -- and, when answer sets are blocked, atoms T p -- under
-            // Res-learning for literals of either sign)
-            unsigned long long d;
-            int s0, cs;
             if (inl) {
-                d = selfd;
-                if (e.o1 != 0 && lvar(e.o1) != x) d |= c.deps[lvar(e.o1)];
-                if (e.o2 != 0 && lvar(e.o2) != x) d |= c.deps[lvar(e.o2)];
-                s0 = u == e.o1 ? e.a1 : e.a2;
-                cs = u == e.o1 ? e.n1 : e.n2;
+                if (e.o1 != 0 && lvar(e.o1) != x) dA = c.deps[lvar(e.o1)];
+                if (e.o2 != 0 && lvar(e.o2) != x) dB = c.deps[lvar(e.o2)];
             } else {
-                d = 0ull;
                 for (int q = 0; q < len; ++q) {
                     const int y = lvar(lits[q]);
-                    if (y != x) d |= c.deps[y];
+                    if (y != x) dA |= c.deps[y];
                 }
                 const int li = 2 * x + (code == VF ? 1 : 0);
                 s0 = c.MO[li];
-                cs = c.MO[li + 1] - s0;
+                s1 = c.MO[li + 1];
             }
-            const bool dec_lit = c.learning == LEARN_RES || (c.ext && code == VT) ||
-                                 (code == VT && x > k.A && (x - k.A - 1) % 3 == 0);
-            const int lli = 2 * x + (code == VF ? 1 : 0);
-            const int l0 = dec_lit ? c.lptr[lli] : 0;
-            const int cl = dec_lit ? c.ln[lli] : 0;
-            const int sl = atomicAdd(&c.scr->nimpl, 1);
-            if (sl < kImplCap) {
-                c.iDeps[sl] = d;
-                c.iS0[sl] = s0;
-                c.iCs[sl] = cs;
-                c.iL0[sl] = l0;
-                c.iCl[sl] = cl;
-                lo = SLOT_TAG | (uint32_t)sl;
+            if (dec_lit) {
+                const int lli = 2 * x + (code == VF ? 1 : 0);
+                l0 = c.lptr[lli];
+                cl = c.ln[lli];
             }
         }
+        int first = 0;
+        const int t = tab_insert(c, x, first);
+        const int sl = c.W == 1 ? atomicAdd(&c.scr->nimpl, 1) : kImplCap;
+        if (sl < kImplCap) {
+            if (inl) {
+                s0 = u == e.o1 ? e.a1 : e.a2;
+                s1 = s0 + (u == e.o1 ? e.n1 : e.n2);
+            }
+            c.iDeps[sl] = (inl ? selfd : 0ull) | dA | dB;
+            c.iS0[sl] = s0;
+            c.iCs[sl] = s1 - s0;
+            c.iL0[sl] = l0;
+            c.iCl[sl] = cl;
+            lo = SLOT_TAG | (uint32_t)sl;
+        }
         const unsigned long long key = ((unsigned long long)hi << 32) | lo;
-        const int t = tab_insert(c, x);
-        if (t >= 0) atomicMin(&c.tWin[t], key);
-        else min_wg(&c.win[x], key);
-        uint32_t sh = (uint32_t)(x & 15) << 1;
-        uint32_t old = atomicOr(&c.pendb[x >> 4], code << sh);
-        uint32_t ob = (old >> sh) & 3u;
-        if (ob == 0u) {
+        // x joins the round's implied variables (the trail) with its first
+        // implier; both values implied for x in one round is a clash.  In
+        // the LDS table the first implier is the lane that inserted x, and
+        // the values seen are OR-ed into the entry's code; past the table,
+        // the pending map plays both parts.
+        int append = 0;
+        if (t >= 0) {
+            atomicMin(&c.tWin[t], key);
+            const uint32_t oc = (uint32_t)atomicOr(&c.tCode[t], (int)code);
+            if ((oc | code) == 3u) c.scr->clash = 1;
+            append = first;
+        } else {
+            min_wg(&c.win[x], key);
+            const uint32_t ob = pend_or(c.pendb, x, code);
+            if (ob == 0u) append = 1;
+            else if ((ob | code) == 3u) c.scr->clash = 1;
+        }
+        if (append) {
             const int pos = atomicAdd(&c.scr->tail, 1);
             c.trail[pos] = x;
             if (pos - k.qt < kFrontCap) c.fNew[pos - k.qt] = x;
-        } else if ((ob | code) == 3u) {
-            c.scr->clash = 1;
         }
     } else {
         const int t = tab_find(c, x);
@@ -932,7 +975,7 @@ DEV void step_round(Ctx& c, Ctl& k) {
             c.reason[x] = id;
         }
         vset(c.valb, x, code);
-        vclr(c.pendb, x);
+        if (t < 0) pend_clr(c.pendb, x);   // only variables past the table use the pending map
     }
     bar();
     const unsigned long long ck = (unsigned long long)uni64((int64_t)c.scr->conf_key);
@@ -942,6 +985,7 @@ DEV void step_round(Ctx& c, Ctl& k) {
             const int t = c.fSlot[i];
             if (t >= 0) {
                 c.tKey[t] = -1;
+                c.tCode[t] = 0;
                 c.tWin[t] = WIN_NONE;
             }
         }
@@ -1721,7 +1765,7 @@ DEV void answer_set(Ctx& c, Ctl& k, const KArgs& a) {
 DEV void step_gate(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model) {
     const int T = c.T, tid = c.tid, W = c.W, A = k.A, Rh = k.Rh;
     at_fixpoint(k);
-    uint32_t* lm = c.pendb;   // 1 bit per atom; the pending map is idle here
+    uint32_t* lm = c.lm;   // 1 bit per atom, zero between checks
     for (;;) {
         c.scr->changed = 0;
         bar();
@@ -1783,8 +1827,7 @@ DEV void step_gate(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model) {
         }
     }
     bar();
-    const int words = (k.V + 1 + 15) >> 4;
-    for (int i = tid; i < words; i += T) lm[i] = 0u;
+    for (int i = tid; i < ((A + 1 + 31) >> 5); i += T) lm[i] = 0u;
     bar();
     if (u == 0x7fffffff) {
         answer_set(c, k, a);
@@ -1912,15 +1955,17 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void 
     c.scr = &scr;
     c.my_visits = c.my_checks = 0ull;
     {
+        // 8-byte arrays first (the base is 8-byte aligned), then 4-byte ones
         unsigned char* p = (unsigned char*)smem64;
-        c.valb = (uint32_t*)p; p += sizeof(uint32_t) * a.words;
-        c.pendb = (uint32_t*)p; p += sizeof(uint32_t) * a.words;
         c.sB = (unsigned long long*)p; p += sizeof(unsigned long long) * kMaxW;
         c.tWin = (unsigned long long*)p; p += sizeof(unsigned long long) * kWinCap;
         c.iDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * kImplCap;
         c.fDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * kFrontCap;
         c.sDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * MAXT;
+        c.valb = (uint32_t*)p; p += sizeof(uint32_t) * a.words;
+        c.lm = (uint32_t*)p; p += sizeof(uint32_t) * a.awords;
         c.tKey = (int32_t*)p; p += sizeof(int32_t) * kWinCap;
+        c.tCode = (int32_t*)p; p += sizeof(int32_t) * kWinCap;
         c.iS0 = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
         c.iCs = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
         c.iL0 = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
@@ -1962,10 +2007,10 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void 
 }
 
 // ------------------------------------------------------------ launchers
-size_t lds_bytes(int threads, int words) {
-    return sizeof(uint32_t) * 2 * (size_t)words + sizeof(unsigned long long) * kMaxW +
+size_t lds_bytes(int threads, int words, int awords) {
+    return sizeof(uint32_t) * ((size_t)words + (size_t)awords) + sizeof(unsigned long long) * kMaxW +
            sizeof(int32_t) * 4 * (size_t)threads + sizeof(int32_t) * 6 * (size_t)kFrontCap +
-           (sizeof(unsigned long long) + sizeof(int32_t)) * (size_t)kWinCap +
+           (sizeof(unsigned long long) + 2 * sizeof(int32_t)) * (size_t)kWinCap +
            (sizeof(unsigned long long) + 4 * sizeof(int32_t)) * (size_t)kImplCap +
            sizeof(unsigned long long) * ((size_t)kFrontCap + (size_t)threads);
 }

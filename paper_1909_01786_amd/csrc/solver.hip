@@ -784,7 +784,10 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
         if (append) {
             const int pos = atomicAdd(&c.scr->tail, 1);
             c.trail[pos] = x;
-            if (pos - k.qt < kFrontCap) c.fNew[pos - k.qt] = x;
+            if (pos - k.qt < kFrontCap) {
+                c.fNew[pos - k.qt] = x;
+                c.fSlot[pos - k.qt] = t;
+            }
         }
     } else {
         const int t = tab_find(c, x);
@@ -907,21 +910,28 @@ DEV void step_round(Ctx& c, Ctl& k) {
     const int nt = uni(c.scr->tail);
     // apply every implication, its Deps being the OR of the Deps of the
     // other variables of the winning nogood (mk_dl_bitmap).  The implied
-    // variables come from LDS when they fit, and so does the winner: its
-    // key from the LDS table, its Deps and frontier record from its slot;
-    // the apply also writes the next round's frontier records
+    // variables come from LDS when they fit (with their winner-table
+    // entries, recorded by the lanes that appended them), and so does the
+    // winner: its key from the LDS table, its Deps and frontier record from
+    // its slot; the apply also writes the next round's frontier records.
+    // When the implied variables fit, no lane searches the table here, so
+    // each lane empties the entries it has read.
     const bool rec = nt - qt <= kFrontCap;
     for (int i = qt + tid; i < nt; i += T) {
         const int x = rec ? c.fNew[i - qt] : c.trail[i];
-        const int t = tab_find(c, x);
+        const int t = rec ? c.fSlot[i - qt] : tab_find(c, x);
         unsigned long long key;
         if (t >= 0) {
             key = c.tWin[t];
+            if (rec) {
+                c.tKey[t] = -1;
+                c.tCode[t] = 0;
+                c.tWin[t] = WIN_NONE;
+            }
         } else {
             key = ld_wg(&c.win[x]);
             st_wg(&c.win[x], WIN_NONE);
         }
-        if (rec) c.fSlot[i - qt] = t;
         const int id = (int)(key >> 33);
         const uint32_t code = ((key >> 32) & 1ull) ? VF : VT;
         const uint32_t lo = (uint32_t)key;
@@ -980,18 +990,7 @@ DEV void step_round(Ctx& c, Ctl& k) {
     bar();
     const unsigned long long ck = (unsigned long long)uni64((int64_t)c.scr->conf_key);
     // the winner table is empty again for the next round
-    if (rec) {
-        for (int i = tid; i < nt - qt; i += T) {
-            const int t = c.fSlot[i];
-            if (t >= 0) {
-                c.tKey[t] = -1;
-                c.tCode[t] = 0;
-                c.tWin[t] = WIN_NONE;
-            }
-        }
-    } else {
-        tab_clear_all(c);
-    }
+    if (!rec) tab_clear_all(c);
     // (the step loop's barrier orders the table clearing before the next use)
     k.qh = qt;
     k.qt = nt;
@@ -1842,6 +1841,18 @@ DEV void step_gate(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model) {
 // the next step is not allowed (step kernels).
 DEV void run_search(Ctx& c, Ctl& k, const KArgs& a, uint8_t* model, uint64_t t0) {
     for (;;) {
+        {
+            // The thread index passes through an empty asm statement at each
+            // step, so the compiler derives the lanes' LDS addresses inside
+            // the step instead of keeping dozens of them live across the
+            // whole search loop (the registers that buy a fourth wave per
+            // SIMD).
+            int t = c.tid;
+            asm volatile("" : "+v"(t));
+            c.tid = t;
+            c.lane = t & 63;
+            c.wid = t >> 6;
+        }
         int halt = 0;
         if (k.status == ST_RUNNING) {
             if (a.mode == MODE_STEPS) {
@@ -1927,14 +1938,14 @@ DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a, uint64_t t0) {
     bar();
 }
 
-// Three waves per SIMD: the register budget (168 VGPRs) at which the
-// search keeps six 128-thread workgroups resident per CU.  The Learning
+// Four waves per SIMD: the register budget (128 VGPRs) at which the
+// search keeps eight 128-thread workgroups resident per CU (LDS allowing).  The Learning
 // step and the search mode are compile-time parameters -- EN 0 plain, 1
 // extended (several answer sets, restarts, the activity Decision), 2 the
 // extended search learning several conflicts per step -- so each search
 // carries only its own code and registers.
 template <int MAXT, int LR, int EN>
-__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3))) void k_search(KArgs a) {
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(4))) void k_search(KArgs a) {
     HIP_DYNAMIC_SHARED(unsigned long long, smem64);  // 8-byte aligned base
     __shared__ Scr scr;
     Ctx c;

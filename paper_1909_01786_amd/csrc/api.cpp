@@ -98,7 +98,7 @@ struct Plan {
     std::vector<int64_t> slot_off;      // per instance, bytes from off_slots
     uint64_t off_desc = 0, off_order = 0, off_slotoff = 0, off_ngo = 0, off_ngl = 0, off_mo = 0,
              off_mi = 0, off_rh = 0, off_ro = 0, off_rbo = 0, off_rbl = 0, off_asc = 0,
-             off_rs = 0, off_verd = 0, off_stats = 0, off_models = 0, off_slots = 0, total = 0;
+             off_rs = 0, off_rord = 0, off_verd = 0, off_stats = 0, off_models = 0, off_slots = 0, total = 0;
     int64_t tot_ngo = 0, tot_ngl = 0, tot_mo = 0, tot_mi = 0, tot_rules = 0, tot_rbo = 0,
             tot_rbl = 0, tot_model = 0, tot_asc = 0, slots_bytes = 0;
     size_t max_lds() const {
@@ -298,6 +298,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.off_rbl = take(4 * (uint64_t)P.tot_rbl);
     P.off_asc = take(4 * (uint64_t)P.tot_asc);
     P.off_rs = take(4 * (uint64_t)P.tot_rules);
+    P.off_rord = take(8 * (uint64_t)P.tot_rules);
     P.off_verd = take(4 * (uint64_t)P.n);
     P.off_stats = take(sizeof(DevStats) * (uint64_t)P.n);
     P.off_models = take((uint64_t)P.tot_model + 1);
@@ -333,6 +334,9 @@ int32_t upload_static(const std::vector<const HostProgram*>& progs, const Plan& 
     // Decision's fallback)
     std::vector<int32_t> ro = concat(progs, P.decision == ASP_DECISION_JW ? &HostProgram::rule_jw
                                                                            : &HostProgram::rule_occ);
+    std::vector<int32_t> rord = concat(progs, P.decision == ASP_DECISION_JW
+                                                  ? &HostProgram::rule_by_jw
+                                                  : &HostProgram::rule_by_occ);
     std::vector<int32_t> rbo = concat(progs, &HostProgram::rb_off);
     std::vector<int32_t> rbl = concat(progs, &HostProgram::rb_lits);
     HIPCHK(put(P.off_desc, P.desc.data(), sizeof(InstDesc) * P.desc.size()));
@@ -344,6 +348,7 @@ int32_t upload_static(const std::vector<const HostProgram*>& progs, const Plan& 
     HIPCHK(put(P.off_mi, mi.data(), sizeof(MapEntry) * mi.size()));
     HIPCHK(put(P.off_rh, rh.data(), 4 * rh.size()));
     HIPCHK(put(P.off_ro, ro.data(), 4 * ro.size()));
+    HIPCHK(put(P.off_rord, rord.data(), 4 * rord.size()));
     HIPCHK(put(P.off_rbo, rbo.data(), 4 * rbo.size()));
     HIPCHK(put(P.off_rbl, rbl.data(), 4 * rbl.size()));
     HIPCHK(hipStreamSynchronize(s));  // host staging vectors die here
@@ -364,6 +369,7 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& 
     a.rule_head = (const int32_t*)(arena + P.off_rh);
     a.rule_occ = (const int32_t*)(arena + P.off_ro);
     a.rule_score = (const int32_t*)(arena + P.off_rs);
+    a.rule_ord = (const int32_t*)(arena + P.off_rord);
     a.rb_off = (const int32_t*)(arena + P.off_rbo);
     a.rb_lits = (const int32_t*)(arena + P.off_rbl);
     a.slots = arena + P.off_slots;
@@ -710,6 +716,7 @@ int32_t upload_one(const HostProgram& h, const Plan& P, int32_t decision, uint8_
         return hipMemcpyAsync(arena + off, src, bytes, hipMemcpyHostToDevice, s);
     };
     const std::vector<int32_t>& ro = decision == ASP_DECISION_JW ? h.rule_jw : h.rule_occ;
+    const std::vector<int32_t>& rord = decision == ASP_DECISION_JW ? h.rule_by_jw : h.rule_by_occ;
     HIPCHK(put(P.off_desc, P.desc.data(), sizeof(InstDesc) * P.desc.size()));
     HIPCHK(put(P.off_order, P.order.data(), 4 * P.order.size()));
     HIPCHK(put(P.off_slotoff, P.slot_off.data(), 8 * P.slot_off.size()));
@@ -719,6 +726,7 @@ int32_t upload_one(const HostProgram& h, const Plan& P, int32_t decision, uint8_
     HIPCHK(put(P.off_mi, h.map_ent.data(), sizeof(MapEntry) * h.map_ent.size()));
     HIPCHK(put(P.off_rh, h.rule_head.data(), 4 * h.rule_head.size()));
     HIPCHK(put(P.off_ro, ro.data(), 4 * ro.size()));
+    HIPCHK(put(P.off_rord, rord.data(), 4 * rord.size()));
     HIPCHK(put(P.off_rbo, h.rb_off.data(), 4 * h.rb_off.size()));
     HIPCHK(put(P.off_rbl, h.rb_lits.data(), 4 * h.rb_lits.size()));
     return ASP_OK;

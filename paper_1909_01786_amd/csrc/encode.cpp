@@ -221,6 +221,20 @@ int encode_program(int32_t n_atoms, int32_t n_rules, const int32_t* head,
         for (int32_t q : hb[j].neg) P->rb_lits.push_back(-q);
         P->rb_off[j + 1] = (int32_t)P->rb_lits.size();
     }
+    auto by_score = [&](const std::vector<int32_t>& sc, std::vector<int32_t>& out) {
+        std::vector<int32_t> ord(Rh);
+        for (int64_t j = 0; j < Rh; ++j) ord[j] = (int32_t)j;
+        std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+            return sc[a] != sc[b] ? sc[a] > sc[b] : a < b;
+        });
+        out.resize(2 * Rh);
+        for (int64_t p = 0; p < Rh; ++p) {
+            out[2 * p] = ord[p];
+            out[2 * p + 1] = hh[ord[p]];
+        }
+    };
+    by_score(P->rule_occ, P->rule_by_occ);
+    by_score(P->rule_jw, P->rule_by_jw);
     return 0;
 }
 

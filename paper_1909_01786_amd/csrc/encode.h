@@ -21,6 +21,9 @@ struct HostProgram {
     std::vector<int32_t> rule_head;      // per headed rule
     std::vector<int32_t> rule_occ;       // occurrence count of the head in Delta_0
     std::vector<int32_t> rule_jw;        // Jeroslow-Wang score of the head (fixed point)
+    // the rules by score, descending, then by rule, ascending, as (rule, head)
+    // pairs: the order in which the Decision prefers them under either score
+    std::vector<int32_t> rule_by_occ, rule_by_jw;
     std::vector<int32_t> rb_off;         // per headed rule body (deduplicated)
     std::vector<int32_t> rb_lits;
     int64_t n_nogoods() const { return (int64_t)ng_off.size() - 1; }

@@ -89,7 +89,7 @@ struct Scr {
 
 struct Ctx {
     // per-instance static arrays
-    const int32_t *NO, *NL, *MO, *RH, *RO, *RS, *RBO, *RBL;
+    const int32_t *NO, *NL, *MO, *RH, *RO, *RS, *RD, *RBO, *RBL;
     const MapEntry* ME;
     // per-slot arrays
     SlotCtrl* ctrl;
@@ -372,6 +372,7 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     c.RH = a.rule_head + d.rules;
     c.RO = a.rule_occ + d.rules;
     c.RS = a.rule_score + d.rules;
+    c.RD = a.rule_ord + 2 * d.rules;
     c.RBO = a.rb_off + d.rb_off;
     c.RBL = a.rb_lits + d.rb_lits;
     c.ctrl = (SlotCtrl*)(slot + lay.ctrl);
@@ -1545,6 +1546,45 @@ DEV unsigned long long best_rule(Ctx& c, const Ctl& k, const int32_t* score,
     return best;
 }
 
+// The Decision under the static per-rule score: the first candidate in the
+// host's order of the rules (score descending, then rule ascending) is the
+// candidate of greatest (score, -rule) key, the one best_rule finds.  Each
+// wave scans its own 64-position chunks of that order (wave w: chunks w,
+// w + nw, ...), four in flight, and stops at its first chunk that holds a
+// candidate; the block keeps the lowest position.  Returns
+// (2^32-1 - position) << 32 | rule for the caller's block maximum, 0 when no
+// rule is a candidate.
+DEV unsigned long long first_rule(Ctx& c, const Ctl& k) {
+    const int Rh = k.Rh, A = k.A, nw = c.nw, lane = c.lane;
+    constexpr int U = 4;
+    for (int p0 = c.wid * 64; p0 < Rh; p0 += U * nw * 64) {
+        int jj[U], hh[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = p0 + u * nw * 64 + lane;
+            jj[u] = p < Rh ? c.RD[2 * p] : 0;
+            hh[u] = p < Rh ? c.RD[2 * p + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = p0 + u * nw * 64 + lane;
+            bool cand = false;
+            if (p < Rh && vget(c.valb, hh[u]) == 0u) {
+                const int t = A + 3 * jj[u] + 2;
+                cand = vget(c.valb, t) == VT && vget(c.valb, t + 1) != VF;
+            }
+            const unsigned long long m = __ballot(cand);
+            if (m != 0ull) {
+                const int l = __ffsll((long long)m) - 1;
+                const uint32_t pos = (uint32_t)(p0 + u * nw * 64 + l);
+                const int j = __builtin_amdgcn_readlane(jj[u], l);
+                return ((unsigned long long)(0xffffffffu - pos) << 32) | (uint32_t)j;
+            }
+        }
+    }
+    return 0ull;
+}
+
 // Assign T b_j at the next level (the decided literal; its Deps is the
 // level's bit) and make it the frontier.  Counters and trace untouched.
 DEV void decide_rule(Ctx& c, Ctl& k, int j) {
@@ -1645,18 +1685,24 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
     // the score is the static per-rule table (occurrences or Jeroslow-Wang),
     // the supplied scores, or the head's activity
     const int32_t* score = k.use_score ? c.RS : c.RO;
-    const unsigned long long mine = c.ext && c.decision == DECISION_ACTIVITY
-                                        ? best_rule<true>(c, k, c.RO)
-                                        : best_rule<false>(c, k, score);
-    unsigned long long best = mine;
-    best = block_max_u64(c, best);
+    unsigned long long best;
+    int j;
+    if (!c.ext && !k.use_score) {
+        best = block_max_u64(c, first_rule(c, k));
+        j = (int)(uint32_t)(best & 0xffffffffull);
+    } else {
+        const unsigned long long mine = c.ext && c.decision == DECISION_ACTIVITY
+                                            ? best_rule<true>(c, k, c.RO)
+                                            : best_rule<false>(c, k, score);
+        best = block_max_u64(c, mine);
+        j = rule_of(best);
+    }
     bar();
     if (best != 0ull) {
         if (c.ext && c.lookahead > 1) {
             lookahead_decide(c, k, best, score);
             return STEP_DECIDE;
         }
-        const int j = rule_of(best);
         decide_rule(c, k, j);
         k.decisions += 1;
         k.dec_open = 1;
@@ -1938,14 +1984,16 @@ DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a, uint64_t t0) {
     bar();
 }
 
-// Four waves per SIMD: the register budget (128 VGPRs) at which the
-// search keeps eight 128-thread workgroups resident per CU (LDS allowing).  The Learning
+// Four waves per SIMD for the plain search: the register budget (128
+// VGPRs) at which it keeps eight 128-thread workgroups resident per CU (LDS
+// allowing); the extended search, with more live state, keeps three (168
+// VGPRs) rather than spill.  The Learning
 // step and the search mode are compile-time parameters -- EN 0 plain, 1
 // extended (several answer sets, restarts, the activity Decision), 2 the
 // extended search learning several conflicts per step -- so each search
 // carries only its own code and registers.
 template <int MAXT, int LR, int EN>
-__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(4))) void k_search(KArgs a) {
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(EN == 0 ? 4 : 3))) void k_search(KArgs a) {
     HIP_DYNAMIC_SHARED(unsigned long long, smem64);  // 8-byte aligned base
     __shared__ Scr scr;
     Ctx c;

@@ -1984,16 +1984,16 @@ DEV void write_result(Ctx& c, const Ctl& k, const KArgs& a, uint64_t t0) {
     bar();
 }
 
-// Four waves per SIMD for the plain search: the register budget (128
-// VGPRs) at which it keeps eight 128-thread workgroups resident per CU (LDS
-// allowing); the extended search, with more live state, keeps three (168
-// VGPRs) rather than spill.  The Learning
+// Four waves per SIMD for the plain search with Fwd-learning: the register
+// budget (128 VGPRs) at which it keeps eight 128-thread workgroups resident
+// per CU (LDS allowing); Res-learning and the extended search, with more
+// live state, keep three (168 VGPRs) rather than spill.  The Learning
 // step and the search mode are compile-time parameters -- EN 0 plain, 1
 // extended (several answer sets, restarts, the activity Decision), 2 the
 // extended search learning several conflicts per step -- so each search
 // carries only its own code and registers.
 template <int MAXT, int LR, int EN>
-__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(EN == 0 ? 4 : 3))) void k_search(KArgs a) {
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 && LR == 0) ? 4 : 3))) void k_search(KArgs a) {
     HIP_DYNAMIC_SHARED(unsigned long long, smem64);  // 8-byte aligned base
     __shared__ Scr scr;
     Ctx c;

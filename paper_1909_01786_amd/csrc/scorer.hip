@@ -7,18 +7,20 @@
 // activations are integer codes 0..255 and weights integer codes -127..127,
 // both held as bfloat16; a 64-term product of them is an integer below 2^21,
 // exact in the float32 accumulator of the matrix cores whatever the order of
-// its sums.  Edge sums are integer atomics in LDS (order-free as well), and
-// the requantisation act(z) = min(255, (z + 256) >> 9) for z > 0 is integer.
+// its sums.  Edge terms are integer too (below), and the requantisation
+// act(z) = min(255, (z + 256) >> 9) for z > 0 is integer.
 //
 // Work is cut into tiles of 64 rows of one instance (variables, or static
 // nogoods), one workgroup of four waves per tile, tiles taken grid-stride so
-// each workgroup stages the layer's weights into LDS once.  A tile's edges
-// are taken 64 at a time: their source rows are gathered into an LDS operand
-// tile, multiplied by both sign matrices on the matrix cores (32x32x16 bf16
-// blocks, two per wave), and each product row is added into its owner's
-// int64 accumulator when its sign matches.  The epilogue multiplies the
-// tile's own rows by the self matrix, adds the normalised edge sum and the
-// bias, requantises, and stores the 64 codes per row.
+// each workgroup stages the layer's weights into LDS once.  Each row's edge
+// sources are summed first (four threads per row, 16 columns each, the
+// positive and the negative edges apart), and the sums are multiplied once
+// by both sign matrices stacked along K on the matrix cores (32x32x16 bf16
+// blocks), in base-256 limbs so that every operand is exact in bfloat16 --
+// by linearity the same integer as summing every edge's product, with no
+// per-edge products and no atomics.  The epilogue multiplies the tile's own
+// rows by the self matrix, adds the normalised edge term and the bias,
+// requantises, and stores the 64 codes per row.
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -86,6 +88,37 @@ DEV void stage_t(uint16_t* BT, const uint16_t* M, int tid) {
     }
 }
 
+// Both sign matrices side by side along K: operand rows of 2H values (the
+// positive-edge sums, then the negative-edge sums) times [M+; M-].
+constexpr int K2 = 2 * H;
+constexpr int LD2 = K2 + 8;       // LDS row stride of the 2H-wide tiles (16-byte rows)
+
+// One 32x32 block of a 2H-wide operand tile (stride LD2) times 32 output
+// columns given as rows of the transposed stacked weights (stride LD2).
+DEV v16f mma_block2(const uint16_t* A, const uint16_t* BT, int lane) {
+    v16f acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    const int i = lane & 31, kh = (lane >> 5) * 8;
+#pragma unroll
+    for (int k0 = 0; k0 < K2; k0 += 16) {
+        const v8bf x = *(const v8bf*)(A + i * LD2 + k0 + kh);
+        const v8bf y = *(const v8bf*)(BT + i * LD2 + k0 + kh);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// BT[j][m H + k] = M_m[k][j] for the [64][64] matrices M_0 (positive edges)
+// and M_1 (negative edges) held in global memory.
+DEV void stage_t2(uint16_t* BT, const uint16_t* M0, const uint16_t* M1, int tid) {
+    for (int idx = tid; idx < 2 * H * H; idx += NT) {
+        const int m = idx >= H * H ? 1 : 0, r = idx - m * H * H;
+        const int k = r >> 6, j = r & 63;
+        BT[j * LD2 + m * H + k] = (m ? M1 : M0)[k * H + j];
+    }
+}
+
 // 16 activation codes from global memory as bfloat16 into an operand row.
 DEV void load_codes16(uint16_t* dst, const uint8_t* src) {
     const uint4 q = *(const uint4*)src;
@@ -101,60 +134,90 @@ DEV void zero16(uint16_t* dst) {
     for (int t = 0; t < 16; ++t) dst[t] = 0;
 }
 
-// LDS of the layer kernels (dynamic, 8-byte aligned base).
+// 16 codes (bytes of a row quarter) added into 16 integer sums.
+DEV void add_codes16(int* s, const uint4 q) {
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) s[4 * b + t] += (int)((w[b] >> (8 * t)) & 255u);
+}
+
+// LDS of the layer kernels (dynamic, 16-byte aligned base).
 struct LayerLds {
-    unsigned long long* acc;   // [TR][H] edge sums
-    uint16_t* wt;              // [2H][LD] both sign matrices, transposed
+    uint16_t* wt;              // [H][LD2] both sign matrices, stacked along K, transposed
     uint16_t* st;              // [H][LD] self matrix, transposed
-    uint16_t* opa;             // [TR][LD] operand tile; the output codes alias it
+    uint16_t* opa;             // [TR][LD2] operand tile: sum limbs, then (stride LD) the
+                               // tile's own rows; the output codes alias it
     int32_t* start;            // [2TR+1] segment starts
-    int32_t* own;              // [TR] owner row of each gathered edge
-    int32_t* pos;              // [TR] 1 if the edge's literal is positive
     int32_t* bias;             // [H]
+    int32_t* smax;             // [1] largest edge sum of the tile
 };
 
-constexpr size_t kLayerLds = sizeof(unsigned long long) * TR * H + sizeof(uint16_t) * 2 * H * LD +
-                             sizeof(uint16_t) * H * LD + sizeof(uint16_t) * TR * LD +
-                             sizeof(int32_t) * (2 * TR + 1 + TR + TR + H) + 16;
+constexpr size_t kLayerLds = sizeof(uint16_t) * H * LD2 + sizeof(uint16_t) * H * LD +
+                             sizeof(uint16_t) * TR * LD2 + sizeof(int32_t) * (2 * TR + 1 + H + 1) + 16;
 
-DEV LayerLds carve(unsigned long long* base) {
+DEV LayerLds carve(unsigned char* p) {
     LayerLds L;
-    unsigned char* p = (unsigned char*)base;
-    L.acc = (unsigned long long*)p; p += sizeof(unsigned long long) * TR * H;
-    L.wt = (uint16_t*)p; p += sizeof(uint16_t) * 2 * H * LD;
+    L.wt = (uint16_t*)p; p += sizeof(uint16_t) * H * LD2;
     L.st = (uint16_t*)p; p += sizeof(uint16_t) * H * LD;
-    L.opa = (uint16_t*)p; p += sizeof(uint16_t) * TR * LD;
+    L.opa = (uint16_t*)p; p += sizeof(uint16_t) * TR * LD2;
     L.start = (int32_t*)p; p += sizeof(int32_t) * (2 * TR + 1);
-    L.own = (int32_t*)p; p += sizeof(int32_t) * TR;
-    L.pos = (int32_t*)p; p += sizeof(int32_t) * TR;
-    L.bias = (int32_t*)p;
+    L.bias = (int32_t*)p; p += sizeof(int32_t) * H;
+    L.smax = (int32_t*)p;
     return L;
 }
 
-// Multiply the gathered operand rows [0, ne) by both sign matrices and add
-// each product row into its owner's accumulator when the sign matches.
-DEV void edge_products(const LayerLds& L, int ne, int tid) {
+// The edge term of a tile: for each row, the sums of its neighbours' code
+// rows over its positive and over its negative edges (thread: one row, one
+// quarter of the columns), times [M+; M-] on the matrix cores.  A product
+// is linear, so this equals the sum of every edge's own product.  The sums
+// (up to 255 per edge) are split into base-256 limbs, each exact in
+// bfloat16; a limb's product (|.| <= 255 * 127 * 2H < 2^24) is exact in the
+// float32 accumulator, and the limbs recombine in 64-bit integers.  Returns
+// this lane's 16 elements of its wave's 32x32 output block.
+template <class Edges>
+DEV void edge_term(const LayerLds& L, int rows, Edges edges, int tid, long long* tot) {
     const int w = tid >> 6, lane = tid & 63;
-    const int rb = w & 1, sg = w >> 1;            // sg 0: positive matrix, 1: negative
+    const int r = 16 * w + (lane >> 2), q = lane & 3;
+    int sp[16], sn[16];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-        const v16f o = mma_block(L.opa + 32 * rb * LD, L.wt + (sg * H + cb * 32) * LD, lane);
+    for (int t = 0; t < 16; ++t) sp[t] = sn[t] = 0;
+    if (r < rows) edges(r, q, sp, sn);
+    int mx = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 32 * rb + blk_row(r, lane);
-            if (row < ne && L.pos[row] == 1 - sg)
-                atomicAdd(&L.acc[L.own[row] * H + cb * 32 + (lane & 31)],
-                          (unsigned long long)(long long)(int)o[r]);
+    for (int t = 0; t < 16; ++t) mx = max(mx, max(sp[t], sn[t]));
+    if (tid == 0) *L.smax = 0;
+    __syncthreads();
+    atomicMax(L.smax, mx);
+    __syncthreads();
+    const int top = *L.smax;
+    const int nl = top < (1 << 8) ? 1 : top < (1 << 16) ? 2 : top < (1 << 24) ? 3 : 4;
+    const int rb = w & 1, cb = w >> 1;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) tot[t] = 0;
+    for (int li = 0; li < nl; ++li) {
+        uint16_t* row = L.opa + r * LD2 + 16 * q;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            row[t] = code_bf16(((uint32_t)sp[t] >> (8 * li)) & 255u);
+            row[H + t] = code_bf16(((uint32_t)sn[t] >> (8 * li)) & 255u);
         }
+        __syncthreads();
+        const v16f o = mma_block2(L.opa + 32 * rb * LD2, L.wt + 32 * cb * LD2, lane);
+#pragma unroll
+        for (int t = 0; t < 16; ++t) tot[t] += (long long)(int)o[t] * (1LL << (8 * li));
+        __syncthreads();
     }
 }
 
-// Epilogue: own rows (already in the operand tile) times the self matrix,
-// plus the normalised edge sums and the bias, requantised into `out` rows.
-// seg_len(row) gives the normaliser; rows >= rows_n are not written.
+// Epilogue: own rows (loaded into the operand tile at stride LD) times the
+// self matrix, plus the normalised edge term and the bias, requantised into
+// `out` rows.  seg_len(row) gives the normaliser; rows >= rows_n are not
+// written.
 template <class Len>
-DEV void finish_tile(const LayerLds& L, int rows_n, Len seg_len, int zero_row, uint8_t* out,
-                     int tid) {
+DEV void finish_tile(const LayerLds& L, int rows_n, Len seg_len, int zero_row, const long long* tot,
+                     uint8_t* out, int tid) {
     const int w = tid >> 6, lane = tid & 63;
     const int rb = w & 1, cb = w >> 1;
     const v16f o = mma_block(L.opa + 32 * rb * LD, L.st + 32 * cb * LD, lane);
@@ -164,9 +227,7 @@ DEV void finish_tile(const LayerLds& L, int rows_n, Len seg_len, int zero_row, u
     for (int r = 0; r < 16; ++r) {
         const int row = 32 * rb + blk_row(r, lane), col = 32 * cb + (lane & 31);
         if (row < rows_n) {
-            const long long z = (long long)(int)o[r] +
-                                norm_sum((long long)L.acc[row * H + col], seg_len(row)) +
-                                L.bias[col];
+            const long long z = (long long)(int)o[r] + norm_sum(tot[r], seg_len(row)) + L.bias[col];
             codes[row * H + col] = row == zero_row ? (uint8_t)0 : (uint8_t)act(z);
         }
     }
@@ -247,11 +308,11 @@ __global__ __launch_bounds__(NT) void k_embed(ScorerArgs a) {
 // Nogood update of layer l: hc = act(hc S + norm(sum hv P | hv N, |c|) + bc).
 __global__ __launch_bounds__(NT) void k_nogoods(ScorerArgs a, int l) {
     HIP_DYNAMIC_SHARED(uint4, smem16);   // 16-byte aligned base for the bf16 operand rows
-    const LayerLds L = carve((unsigned long long*)smem16);
+    const LayerLds L = carve((unsigned char*)smem16);
     const int tid = threadIdx.x;
     const size_t HH = (size_t)H * H;
-    stage_t(L.wt, wmat(a, offsetof(asp_scorer_weights, P)) + l * HH, tid);
-    stage_t(L.wt + H * LD, wmat(a, offsetof(asp_scorer_weights, N)) + l * HH, tid);
+    stage_t2(L.wt, wmat(a, offsetof(asp_scorer_weights, P)) + l * HH,
+             wmat(a, offsetof(asp_scorer_weights, N)) + l * HH, tid);
     stage_t(L.st, wmat(a, offsetof(asp_scorer_weights, S)) + l * HH, tid);
     for (int i = tid; i < H; i += NT) L.bias[i] = wvec(a, offsetof(asp_scorer_weights, bc))[l * H + i];
     for (int t = blockIdx.x; t < a.n_ctiles; t += gridDim.x) {
@@ -263,36 +324,25 @@ __global__ __launch_bounds__(NT) void k_nogoods(ScorerArgs a, int l) {
         const uint8_t* hv = a.ws + a.hv_off[tl.inst];
         uint8_t* hc = a.ws + a.hc_off[tl.inst] + (size_t)tl.row0 * H;
         for (int i = tid; i <= rows; i += NT) L.start[i] = NO[i];
-        for (int i = tid; i < TR * H; i += NT) L.acc[i] = 0ull;
         __syncthreads();
-        const int e0 = L.start[0], e1 = L.start[rows];
-        const int er = tid >> 2, part = tid & 3;
-        for (int eb = e0; eb < e1; eb += TR) {
-            const int ne = min(TR, e1 - eb);
-            if (er < ne) {
-                const int lit = NL[eb + er];
-                const int v = lit < 0 ? -lit : lit;
-                load_codes16(L.opa + er * LD + part * 16, hv + (size_t)v * H + part * 16);
-                if (part == 0) {
-                    int lo = 0, hi = rows - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (L.start[mid] <= eb + er) lo = mid; else hi = mid - 1;
-                    }
-                    L.own[er] = lo;
-                    L.pos[er] = lit > 0 ? 1 : 0;
-                }
-            } else {
-                zero16(L.opa + er * LD + part * 16);
+        long long tot[16];
+        edge_term(L, rows, [&](int r, int q, int* sp, int* sn) {
+            const int e1 = L.start[r + 1];
+            for (int e = L.start[r]; e < e1; e += 2) {
+                const bool two = e + 1 < e1;
+                const int l0 = NL[e], l1 = two ? NL[e + 1] : 0;
+                const uint4 c0 = *(const uint4*)(hv + (size_t)(l0 < 0 ? -l0 : l0) * H + 16 * q);
+                const uint4 c1 = two ? *(const uint4*)(hv + (size_t)(l1 < 0 ? -l1 : l1) * H + 16 * q)
+                                     : make_uint4(0u, 0u, 0u, 0u);
+                if (l0 > 0) add_codes16(sp, c0); else add_codes16(sn, c0);
+                if (l1 > 0) add_codes16(sp, c1); else add_codes16(sn, c1);
             }
-            __syncthreads();
-            edge_products(L, ne, tid);
-            __syncthreads();
-        }
+        }, tid, tot);
+        const int er = tid >> 2, part = tid & 3;
         if (er < rows) load_codes16(L.opa + er * LD + part * 16, hc + (size_t)er * H + part * 16);
         else zero16(L.opa + er * LD + part * 16);
         __syncthreads();
-        finish_tile(L, rows, [&](int row) { return L.start[row + 1] - L.start[row]; }, -1, hc, tid);
+        finish_tile(L, rows, [&](int row) { return L.start[row + 1] - L.start[row]; }, -1, tot, hc, tid);
         __syncthreads();
     }
 }
@@ -301,12 +351,12 @@ __global__ __launch_bounds__(NT) void k_nogoods(ScorerArgs a, int l) {
 // the last layer also writes each atom's score hv . wo + bo.
 __global__ __launch_bounds__(NT) void k_vars(ScorerArgs a, int l, int last) {
     HIP_DYNAMIC_SHARED(uint4, smem16);   // 16-byte aligned base for the bf16 operand rows
-    const LayerLds L = carve((unsigned long long*)smem16);
+    const LayerLds L = carve((unsigned char*)smem16);
     __shared__ int sWo[H];
     const int tid = threadIdx.x;
     const size_t HH = (size_t)H * H;
-    stage_t(L.wt, wmat(a, offsetof(asp_scorer_weights, Q)) + l * HH, tid);
-    stage_t(L.wt + H * LD, wmat(a, offsetof(asp_scorer_weights, R)) + l * HH, tid);
+    stage_t2(L.wt, wmat(a, offsetof(asp_scorer_weights, Q)) + l * HH,
+             wmat(a, offsetof(asp_scorer_weights, R)) + l * HH, tid);
     stage_t(L.st, wmat(a, offsetof(asp_scorer_weights, T)) + l * HH, tid);
     for (int i = tid; i < H; i += NT) {
         L.bias[i] = wvec(a, offsetof(asp_scorer_weights, bv))[l * H + i];
@@ -323,36 +373,27 @@ __global__ __launch_bounds__(NT) void k_vars(ScorerArgs a, int l, int last) {
         uint8_t* hv = a.ws + a.hv_off[tl.inst] + (size_t)tl.row0 * H;
         const int nseg = 2 * rows;
         for (int i = tid; i <= nseg; i += NT) L.start[i] = MO[i];
-        for (int i = tid; i < TR * H; i += NT) L.acc[i] = 0ull;
         __syncthreads();
-        const int e0 = L.start[0], e1 = L.start[nseg];
-        const int er = tid >> 2, part = tid & 3;
-        for (int eb = e0; eb < e1; eb += TR) {
-            const int ne = min(TR, e1 - eb);
-            if (er < ne) {
-                const int c = ME[eb + er].id;
-                load_codes16(L.opa + er * LD + part * 16, hc + (size_t)c * H + part * 16);
-                if (part == 0) {
-                    int lo = 0, hi = nseg - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (L.start[mid] <= eb + er) lo = mid; else hi = mid - 1;
-                    }
-                    L.own[er] = lo >> 1;
-                    L.pos[er] = (lo & 1) ? 0 : 1;
-                }
-            } else {
-                zero16(L.opa + er * LD + part * 16);
+        long long tot[16];
+        // a variable's positive literal's occurrences, then its negative's
+        edge_term(L, rows, [&](int r, int q, int* sp, int* sn) {
+            const int e1 = L.start[2 * r + 2], em = L.start[2 * r + 1];
+            for (int e = L.start[2 * r]; e < e1; e += 2) {
+                const bool two = e + 1 < e1;
+                const int c0 = ME[e].id, c1 = two ? ME[e + 1].id : 0;
+                const uint4 x0 = *(const uint4*)(hc + (size_t)c0 * H + 16 * q);
+                const uint4 x1 = two ? *(const uint4*)(hc + (size_t)c1 * H + 16 * q)
+                                     : make_uint4(0u, 0u, 0u, 0u);
+                if (e < em) add_codes16(sp, x0); else add_codes16(sn, x0);
+                if (e + 1 < em) add_codes16(sp, x1); else add_codes16(sn, x1);
             }
-            __syncthreads();
-            edge_products(L, ne, tid);
-            __syncthreads();
-        }
+        }, tid, tot);
+        const int er = tid >> 2, part = tid & 3;
         if (er < rows) load_codes16(L.opa + er * LD + part * 16, hv + (size_t)er * H + part * 16);
         else zero16(L.opa + er * LD + part * 16);
         __syncthreads();
         finish_tile(L, rows, [&](int row) { return L.start[2 * row + 2] - L.start[2 * row]; },
-                    tl.row0 == 0 ? 0 : -1, hv, tid);
+                    tl.row0 == 0 ? 0 : -1, tot, hv, tid);
         if (last && tid < rows) {
             const int v = tl.row0 + tid;
             if (v <= d.A) {

@@ -136,6 +136,32 @@ def test_scorer_saturating_weights(P):
     assert np.array_equal(g.score(w), want)
 
 
+def _hub(n):
+    """Atom 1 in the bodies of n rules: its variable has about n edges of
+    one sign, so the scorer's edge sums (up to 255 per edge) need more than
+    two base-256 limbs once n exceeds 257."""
+    rules = [(i, [1]) for i in range(2, n + 2)] + [(1, [-2])]
+    return aspgen.from_rules(n + 1, rules, name=f"hub{n}")
+
+
+@pytest.mark.parametrize("n", [40, 300, 2000])
+@pytest.mark.parametrize("saturate", [False, True])
+def test_scorer_wide_edge_sums_exact(P, n, saturate):
+    """A variable of high degree (one, two and three limbs of the edge
+    sums; saturating weights drive every code to 255): codes equal the
+    oracle's bit for bit."""
+    prog = _hub(n)
+    w = aspgen.mpnn_weights(9)
+    if saturate:
+        for k in ("Ev", "Ec", "P", "N", "S", "Q", "R", "T"):
+            w[k] = np.full_like(w[k], 127)
+        w["wo"] = np.full_like(w["wo"], -127)
+    want = mpnn.scores(w, prog)
+    g = P.Program(prog)
+    g.bind("cuda")
+    assert np.array_equal(g.score(w), want)
+
+
 def test_scorer_batch_and_learned_search_end_to_end(P):
     """Batched scorer over uneven programs, then the score-driven batched
     search: every atom code and every search equals the oracle's."""

@@ -98,7 +98,7 @@ struct Plan {
     std::vector<int64_t> slot_off;      // per instance, bytes from off_slots
     uint64_t off_desc = 0, off_order = 0, off_slotoff = 0, off_ngo = 0, off_ngl = 0, off_mo = 0,
              off_mi = 0, off_rh = 0, off_ro = 0, off_rbo = 0, off_rbl = 0, off_asc = 0,
-             off_rs = 0, off_rord = 0, off_verd = 0, off_stats = 0, off_models = 0, off_slots = 0, total = 0;
+             off_rs = 0, off_rord = 0, off_rords = 0, off_rsort = 0, off_verd = 0, off_stats = 0, off_models = 0, off_slots = 0, total = 0;
     int64_t tot_ngo = 0, tot_ngl = 0, tot_mo = 0, tot_mi = 0, tot_rules = 0, tot_rbo = 0,
             tot_rbl = 0, tot_model = 0, tot_asc = 0, slots_bytes = 0;
     size_t max_lds() const {
@@ -299,6 +299,8 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
     P.off_asc = take(4 * (uint64_t)P.tot_asc);
     P.off_rs = take(4 * (uint64_t)P.tot_rules);
     P.off_rord = take(8 * (uint64_t)P.tot_rules);
+    P.off_rords = take(8 * (uint64_t)P.tot_rules);
+    P.off_rsort = take(8 * (uint64_t)P.tot_rules);
     P.off_verd = take(4 * (uint64_t)P.n);
     P.off_stats = take(sizeof(DevStats) * (uint64_t)P.n);
     P.off_models = take((uint64_t)P.tot_model + 1);
@@ -370,6 +372,7 @@ KArgs make_args(const Plan& P, uint8_t* arena, int32_t mode, const LaunchClass& 
     a.rule_occ = (const int32_t*)(arena + P.off_ro);
     a.rule_score = (const int32_t*)(arena + P.off_rs);
     a.rule_ord = (const int32_t*)(arena + P.off_rord);
+    a.rule_ord_sc = (const int32_t*)(arena + P.off_rords);
     a.rb_off = (const int32_t*)(arena + P.off_rbo);
     a.rb_lits = (const int32_t*)(arena + P.off_rbl);
     a.slots = arena + P.off_slots;
@@ -520,6 +523,8 @@ int32_t put_scores(const Plan& P, uint8_t* arena, int32_t i, const int32_t* scor
     a.rule_head = (const int32_t*)(arena + P.off_rh);
     a.atom_score = (int32_t*)(arena + P.off_asc);
     a.rule_score = (int32_t*)(arena + P.off_rs);
+    a.rule_ord_sc = (int32_t*)(arena + P.off_rords);
+    a.sort_tmp = (unsigned long long*)(arena + P.off_rsort);
     a.inst_list = nullptr;   // gather instance i only
     a.single = i;
     HIPCHK(launch_rule_scores(a, s));
@@ -669,6 +674,8 @@ ScorerArgs scorer_args(const std::vector<const HostProgram*>& progs, const Plan&
     a.ws = ws;
     a.atom_score = (int32_t*)(arena + P.off_asc);
     a.rule_score = (int32_t*)(arena + P.off_rs);
+    a.rule_ord_sc = (int32_t*)(arena + P.off_rords);
+    a.sort_tmp = (unsigned long long*)(arena + P.off_rsort);
     return a;
 }
 

@@ -178,6 +178,7 @@ struct KArgs {
     const int32_t* rule_occ;
     const int32_t* rule_score;   // score of each rule's head (score-driven Decision)
     const int32_t* rule_ord;     // (rule, head) pairs in the static score's Decision order
+    const int32_t* rule_ord_sc;  // (rule, head) pairs in the supplied scores' Decision order
     const int32_t* rb_off;
     const int32_t* rb_lits;
     uint8_t* slots;              // base of the state slots

@@ -27,6 +27,8 @@ struct ScorerArgs {
     uint8_t* ws;
     int32_t* atom_score;
     int32_t* rule_score;
+    int32_t* rule_ord_sc;              // (rule, head) pairs by rule score, descending
+    unsigned long long* sort_tmp;      // one 8-byte word per rule (sort buffer)
 };
 
 // Readout training state (device pointers into the workspace).

@@ -407,14 +407,82 @@ __global__ __launch_bounds__(NT) void k_vars(ScorerArgs a, int l, int last) {
     }
 }
 
+// The Decision's order of an instance's rules under these scores: rule
+// score descending, then rule ascending, as one ascending 64-bit key
+// (complemented biased score, rule).
+DEV unsigned long long score_key(int score, int j) {
+    return ((unsigned long long)(~((uint32_t)score ^ 0x80000000u)) << 32) | (uint32_t)j;
+}
+
+constexpr int kSortChunk = 1024;
+
 // rule_score[r] = atom_score[head(r)] for every headed rule of the listed
-// instances.
+// instances, and rule_ord_sc = the (rule, head) pairs in the Decision's
+// order under these scores: chunks of kSortChunk keys sorted in LDS by a
+// bitonic network, then merged pairwise in global memory (each key's place
+// in the merged run is its index in its own run plus the number of keys
+// below it in the other run, found by binary search; keys are distinct),
+// alternating between the output array and the sort buffer.
 __global__ __launch_bounds__(NT) void k_rule_scores(ScorerArgs a) {
+    __shared__ unsigned long long sk[kSortChunk];
+    const int tid = threadIdx.x;
     const int n = a.inst_list ? a.n_inst : 1;
     for (int b = blockIdx.x; b < n; b += gridDim.x) {
         const InstDesc& d = a.inst[a.inst_list ? a.inst_list[b] : a.single];
-        for (int j = threadIdx.x; j < d.Rh; j += NT)
-            a.rule_score[d.rules + j] = a.atom_score[d.ascore + a.rule_head[d.rules + j]];
+        const int Rh = d.Rh;
+        unsigned long long* A = (unsigned long long*)(a.rule_ord_sc + 2 * d.rules);
+        unsigned long long* B = a.sort_tmp + d.rules;
+        for (int j = tid; j < Rh; j += NT) {
+            const int sc = a.atom_score[d.ascore + a.rule_head[d.rules + j]];
+            a.rule_score[d.rules + j] = sc;
+            A[j] = score_key(sc, j);
+        }
+        __syncthreads();
+        for (int c0 = 0; c0 < Rh; c0 += kSortChunk) {
+            const int m = min(kSortChunk, Rh - c0);
+            for (int i = tid; i < kSortChunk; i += NT) sk[i] = i < m ? A[c0 + i] : ~0ull;
+            __syncthreads();
+            for (int k = 2; k <= kSortChunk; k <<= 1) {
+                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                    for (int t = tid; t < kSortChunk / 2; t += NT) {
+                        const int i = 2 * jj * (t / jj) + (t % jj), p = i + jj;
+                        const unsigned long long x = sk[i], y = sk[p];
+                        if ((x > y) == ((i & k) == 0)) {
+                            sk[i] = y;
+                            sk[p] = x;
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int i = tid; i < m; i += NT) A[c0 + i] = sk[i];
+            __syncthreads();
+        }
+        unsigned long long *src = A, *dst = B;
+        for (int w = kSortChunk; w < Rh; w *= 2) {
+            for (int i = tid; i < Rh; i += NT) {
+                const int run = i / w, r0 = run * w, ps = (run & ~1) * w;
+                const int o0 = (run & 1) ? r0 - w : r0 + w;          // the other run
+                const int o1 = (run & 1) ? r0 : min(r0 + 2 * w, Rh);
+                const unsigned long long x = src[i];
+                int lo = o0, hi = o0 < o1 ? o1 : o0;                 // first key >= x in [o0, o1)
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (src[mid] < x) lo = mid + 1; else hi = mid;
+                }
+                dst[ps + (i - r0) + (lo - o0)] = x;
+            }
+            __syncthreads();
+            unsigned long long* t = src;
+            src = dst;
+            dst = t;
+        }
+        // (rule, head) pairs in place of the keys
+        for (int p = tid; p < Rh; p += NT) {
+            const int j = (int)(uint32_t)(src[p] & 0xffffffffull);
+            A[p] = ((unsigned long long)(uint32_t)a.rule_head[d.rules + j] << 32) | (uint32_t)j;
+        }
+        __syncthreads();
     }
 }
 

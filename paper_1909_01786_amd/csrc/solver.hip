@@ -89,7 +89,7 @@ struct Scr {
 
 struct Ctx {
     // per-instance static arrays
-    const int32_t *NO, *NL, *MO, *RH, *RO, *RS, *RD, *RBO, *RBL;
+    const int32_t *NO, *NL, *MO, *RH, *RO, *RS, *RD, *RDS, *RBO, *RBL;
     const MapEntry* ME;
     // per-slot arrays
     SlotCtrl* ctrl;
@@ -373,6 +373,7 @@ DEV void bind_instance(Ctx& c, Ctl& k, const KArgs& a, int inst) {
     c.RO = a.rule_occ + d.rules;
     c.RS = a.rule_score + d.rules;
     c.RD = a.rule_ord + 2 * d.rules;
+    c.RDS = a.rule_ord_sc + 2 * d.rules;
     c.RBO = a.rb_off + d.rb_off;
     c.RBL = a.rb_lits + d.rb_lits;
     c.ctrl = (SlotCtrl*)(slot + lay.ctrl);
@@ -1546,15 +1547,17 @@ DEV unsigned long long best_rule(Ctx& c, const Ctl& k, const int32_t* score,
     return best;
 }
 
-// The Decision under the static per-rule score: the first candidate in the
-// host's order of the rules (score descending, then rule ascending) is the
-// candidate of greatest (score, -rule) key, the one best_rule finds.  Each
+// The Decision under a per-rule score that stays fixed during the search
+// (the static table, or supplied scores): the first candidate in the
+// order `ord` of the rules (score descending, then rule ascending; sorted
+// by the host for the static table, on the device for supplied scores) is
+// the candidate of greatest (score, -rule) key, the one best_rule finds.  Each
 // wave scans its own 64-position chunks of that order (wave w: chunks w,
 // w + nw, ...), four in flight, and stops at its first chunk that holds a
 // candidate; the block keeps the lowest position.  Returns
 // (2^32-1 - position) << 32 | rule for the caller's block maximum, 0 when no
 // rule is a candidate.
-DEV unsigned long long first_rule(Ctx& c, const Ctl& k) {
+DEV unsigned long long first_rule(Ctx& c, const Ctl& k, const int32_t* ord) {
     const int Rh = k.Rh, A = k.A, nw = c.nw, lane = c.lane;
     constexpr int U = 4;
     for (int p0 = c.wid * 64; p0 < Rh; p0 += U * nw * 64) {
@@ -1562,8 +1565,8 @@ DEV unsigned long long first_rule(Ctx& c, const Ctl& k) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = p0 + u * nw * 64 + lane;
-            jj[u] = p < Rh ? c.RD[2 * p] : 0;
-            hh[u] = p < Rh ? c.RD[2 * p + 1] : 0;
+            jj[u] = p < Rh ? ord[2 * p] : 0;
+            hh[u] = p < Rh ? ord[2 * p + 1] : 0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1687,8 +1690,8 @@ DEV int step_decide_or_complete(Ctx& c, Ctl& k) {
     const int32_t* score = k.use_score ? c.RS : c.RO;
     unsigned long long best;
     int j;
-    if (!c.ext && !k.use_score) {
-        best = block_max_u64(c, first_rule(c, k));
+    if (!c.ext) {
+        best = block_max_u64(c, first_rule(c, k, k.use_score ? c.RDS : c.RD));
         j = (int)(uint32_t)(best & 0xffffffffull);
     } else {
         const unsigned long long mine = c.ext && c.decision == DECISION_ACTIVITY

@@ -362,7 +362,8 @@ def main():
     ap.add_argument("--max-ms", type=int, default=150000, help="device time guard per launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--learned-steps", type=int, default=1)
+    ap.add_argument("--learned-steps", type=int, default=3,
+                    help="timed steps of the learned leg (its one-step time varies by ~10%%)")
     ap.add_argument("--weights", default=None,
                     help="scorer weight codes (.npz) for the learned legs; default: the trained file")
     ap.add_argument("--no-res", action="store_true", help="skip the Res-learning leg")

@@ -103,7 +103,7 @@ struct Ctx {
     uint32_t* pendb;        // 2-bit pending map past the LDS table (workgroup atomics)
     // LDS
     uint32_t *valb, *lm;
-    int32_t *sOff, *sS0, *sCs, *sL0;
+    int32_t* sOff;
     // frontier records: map segment (start, size) and learned occurrence
     // list (start, size) of each frontier variable's true literal, and the
     // variables the current round implies (in trail order)
@@ -114,9 +114,9 @@ struct Ctx {
     // that applying the winner reads LDS only
     int32_t *tKey, *tCode;
     unsigned long long *tWin, *iDeps;
-    // Deps word of each frontier variable (W = 1), per record and per lane
-    // of the visit pass
-    unsigned long long *fDeps, *sDeps;
+    // Deps word of each frontier variable (W = 1), per record; a T-entry
+    // buffer (Res-learning's rank tiles)
+    unsigned long long *fDeps, *sTile;
     int32_t *iS0, *iCs, *iL0, *iCl;
     unsigned long long* sB;
     Scr* scr;
@@ -801,29 +801,33 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
 
 // Spread the visits of frontier trail[qh..qt) over the block: each frontier
 // variable contributes its static map segment and its learned occurrence
-// list; a scan of the segment sizes gives each lane its visits.
+// list; a scan of the segment sizes gives each lane its visits.  The
+// frontier is taken in chunks of up to kFrontCap variables, whose records
+// (map segment, learned list, Deps word) the visits read from the LDS
+// frontier records: left there by whoever made the frontier, or, when
+// they were not (fr_ok clear), computed into them for the chunk.
 DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
     const int T = c.T, tid = c.tid;
-    for (int base = qh; base < qt; base += T) {
+    const int C = T < kFrontCap ? T : kFrontCap;
+    for (int base = qh; base < qt; base += C) {
         const int f = base + tid;
-        int s0 = 0, cs = 0, l0 = 0, cl = 0;
-        unsigned long long sd = 0ull;
-        if (f < qt) {
+        const int rb = k.fr_ok ? base - qh : 0;   // the chunk's first record
+        int cs = 0, cl = 0;
+        if (tid < C && f < qt) {
             if (k.fr_ok) {
-                s0 = c.fS0[f - qh];
-                cs = c.fCs[f - qh];
-                l0 = c.fL0[f - qh];
-                cl = c.fCl[f - qh];
-                sd = c.fDeps[f - qh];
+                cs = c.fCs[rb + tid];
+                cl = c.fCl[rb + tid];
             } else {
-                int v = c.trail[f];
-                int L = vget(c.valb, v) == VT ? v : -v;
-                int li = lidx(L);
-                s0 = c.MO[li];
+                const int v = c.trail[f];
+                const int L = vget(c.valb, v) == VT ? v : -v;
+                const int li = lidx(L);
+                const int s0 = c.MO[li];
                 cs = c.MO[li + 1] - s0;
-                l0 = c.lptr[li];
                 cl = c.ln[li];
-                sd = c.deps[(size_t)v * c.W];
+                c.fS0[tid] = s0;
+                c.fCs[tid] = cs;
+                c.fL0[tid] = c.lptr[li];
+                c.fDeps[tid] = c.deps[(size_t)v * c.W];
             }
         }
         // wave-local exclusive offsets of the visit counts, and the wave
@@ -831,13 +835,9 @@ DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
         const int cnt_all = cs + cl;
         const int inc = wave_incl_scan(cnt_all);
         c.sOff[tid] = inc - cnt_all;
-        c.sS0[tid] = s0;
-        c.sCs[tid] = cs;
-        c.sL0[tid] = l0;
-        c.sDeps[tid] = sd;
         c.scr->wsum[c.wid] = wave_last(inc);   // identical from the wave's lanes
         bar();
-        const int nf = (qt - base) < T ? (qt - base) : T;
+        const int nf = (qt - base) < C ? (qt - base) : C;
         const int nwv = (nf + 63) >> 6;
         int total = 0;
         for (int w = 0; w < nwv; ++w) total += c.scr->wsum[w];
@@ -863,14 +863,15 @@ DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
             for (int m = 1; m < 8; ++m) r += so[8 * g + m] <= qq ? 1 : 0;
             const int lo = w * 64 + 8 * g + r;
             const int j = qq - c.sOff[lo];
-            const int cnt = c.sCs[lo];
+            const int ri = rb + lo;
+            const int cnt = c.fCs[ri];
             if (j < cnt) {
-                const uint32_t eidx = (uint32_t)(c.sS0[lo] + j);
+                const uint32_t eidx = (uint32_t)(c.fS0[ri] + j);
                 const MapEntry e = c.ME[eidx];
-                visit_one(c, k, e.id, e, eidx, c.sDeps[lo], pass);
+                visit_one(c, k, e.id, e, eidx, c.fDeps[ri], pass);
             } else {
                 const MapEntry none{0, 0, kLongNogood, 0, 0, 0, 0, 0};
-                visit_one(c, k, c.pool[c.sL0[lo] + (j - cnt)], none, NO_ENTRY, c.sDeps[lo], pass);
+                visit_one(c, k, c.pool[c.fL0[ri] + (j - cnt)], none, NO_ENTRY, c.fDeps[ri], pass);
             }
         }
         bar();
@@ -1142,7 +1143,7 @@ DEV int res_learn(Ctx& c, Ctl& k, const KArgs& a, int conf, int base, int top, i
     if (k.n_learned + 1 > a.cap_ng || k.learned_lits + nN > a.cap_lits) return -1;
     // each live variable's rank by (gpos, variable), counted against tiles
     // of the keys staged in LDS
-    unsigned long long* tile = c.sDeps;
+    unsigned long long* tile = c.sTile;
     for (int r = 0; r < nN; r += T) {
         const int i = r + tid;
         const int v = i < nN ? c.resd[i] : 0;
@@ -2023,7 +2024,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 &
         c.tWin = (unsigned long long*)p; p += sizeof(unsigned long long) * kWinCap;
         c.iDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * kImplCap;
         c.fDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * kFrontCap;
-        c.sDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * MAXT;
+        c.sTile = (unsigned long long*)p; p += sizeof(unsigned long long) * MAXT;
         c.valb = (uint32_t*)p; p += sizeof(uint32_t) * a.words;
         c.lm = (uint32_t*)p; p += sizeof(uint32_t) * a.awords;
         c.tKey = (int32_t*)p; p += sizeof(int32_t) * kWinCap;
@@ -2033,9 +2034,6 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 &
         c.iL0 = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
         c.iCl = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
         c.sOff = (int32_t*)p; p += sizeof(int32_t) * MAXT;
-        c.sS0 = (int32_t*)p; p += sizeof(int32_t) * MAXT;
-        c.sCs = (int32_t*)p; p += sizeof(int32_t) * MAXT;
-        c.sL0 = (int32_t*)p; p += sizeof(int32_t) * MAXT;
         c.fS0 = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
         c.fCs = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
         c.fL0 = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
@@ -2071,7 +2069,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 &
 // ------------------------------------------------------------ launchers
 size_t lds_bytes(int threads, int words, int awords) {
     return sizeof(uint32_t) * ((size_t)words + (size_t)awords) + sizeof(unsigned long long) * kMaxW +
-           sizeof(int32_t) * 4 * (size_t)threads + sizeof(int32_t) * 6 * (size_t)kFrontCap +
+           sizeof(int32_t) * (size_t)threads + sizeof(int32_t) * 6 * (size_t)kFrontCap +
            (sizeof(unsigned long long) + 2 * sizeof(int32_t)) * (size_t)kWinCap +
            (sizeof(unsigned long long) + 4 * sizeof(int32_t)) * (size_t)kImplCap +
            sizeof(unsigned long long) * ((size_t)kFrontCap + (size_t)threads);

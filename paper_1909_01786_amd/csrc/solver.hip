@@ -50,7 +50,8 @@ constexpr uint32_t NO_ENTRY = 0xffffffffu;      // implier without a map entry (
 constexpr uint64_t FNV_BASIS = 1469598103934665603ull;
 constexpr uint64_t FNV_PRIME = 1099511628211ull;
 constexpr int kMaxWaves = 16;
-constexpr int kFrontCap = 128;   // frontier records kept in LDS
+constexpr int kFrontCap = 128;   // frontier records kept in LDS (at least; one per thread
+                                 // for wider workgroups)
 constexpr int kWinBits = 8;
 constexpr int kWinCap = 1 << kWinBits;   // LDS winner table (variables implied in a round)
 constexpr int kWinProbe = 32;
@@ -121,6 +122,7 @@ struct Ctx {
     unsigned long long* sB;
     Scr* scr;
     int32_t W, T, tid, lane, wid, nw;
+    int32_t FC;             // frontier records in LDS: max(T, kFrontCap)
     int32_t decision, fallback_after, learning;
     int32_t ext;            // extended search: several answer sets, restarts, activity,
                             // several conflicts learned per step (compile-time in k_search)
@@ -786,7 +788,7 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
         if (append) {
             const int pos = atomicAdd(&c.scr->tail, 1);
             c.trail[pos] = x;
-            if (pos - k.qt < kFrontCap) {
+            if (pos - k.qt < c.FC) {
                 c.fNew[pos - k.qt] = x;
                 c.fSlot[pos - k.qt] = t;
             }
@@ -802,13 +804,13 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
 // Spread the visits of frontier trail[qh..qt) over the block: each frontier
 // variable contributes its static map segment and its learned occurrence
 // list; a scan of the segment sizes gives each lane its visits.  The
-// frontier is taken in chunks of up to kFrontCap variables, whose records
+// frontier is taken in chunks of T variables, whose records
 // (map segment, learned list, Deps word) the visits read from the LDS
 // frontier records: left there by whoever made the frontier, or, when
 // they were not (fr_ok clear), computed into them for the chunk.
 DEV void visit_pass(Ctx& c, const Ctl& k, int qh, int qt, int pass) {
     const int T = c.T, tid = c.tid;
-    const int C = T < kFrontCap ? T : kFrontCap;
+    const int C = T;   // <= c.FC
     for (int base = qh; base < qt; base += C) {
         const int f = base + tid;
         const int rb = k.fr_ok ? base - qh : 0;   // the chunk's first record
@@ -919,7 +921,7 @@ DEV void step_round(Ctx& c, Ctl& k) {
     // its slot; the apply also writes the next round's frontier records.
     // When the implied variables fit, no lane searches the table here, so
     // each lane empties the entries it has read.
-    const bool rec = nt - qt <= kFrontCap;
+    const bool rec = nt - qt <= c.FC;
     for (int i = qt + tid; i < nt; i += T) {
         const int x = rec ? c.fNew[i - qt] : c.trail[i];
         const int t = rec ? c.fSlot[i - qt] : tab_find(c, x);
@@ -2015,6 +2017,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 &
     c.lane = threadIdx.x & 63;
     c.wid = threadIdx.x >> 6;
     c.nw = MAXT / 64;
+    c.FC = MAXT > kFrontCap ? MAXT : kFrontCap;
     c.scr = &scr;
     c.my_visits = c.my_checks = 0ull;
     {
@@ -2023,7 +2026,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 &
         c.sB = (unsigned long long*)p; p += sizeof(unsigned long long) * kMaxW;
         c.tWin = (unsigned long long*)p; p += sizeof(unsigned long long) * kWinCap;
         c.iDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * kImplCap;
-        c.fDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * kFrontCap;
+        c.fDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * c.FC;
         c.sTile = (unsigned long long*)p; p += sizeof(unsigned long long) * MAXT;
         c.valb = (uint32_t*)p; p += sizeof(uint32_t) * a.words;
         c.lm = (uint32_t*)p; p += sizeof(uint32_t) * a.awords;
@@ -2034,12 +2037,12 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 &
         c.iL0 = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
         c.iCl = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
         c.sOff = (int32_t*)p; p += sizeof(int32_t) * MAXT;
-        c.fS0 = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
-        c.fCs = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
-        c.fL0 = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
-        c.fCl = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
-        c.fNew = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
-        c.fSlot = (int32_t*)p; p += sizeof(int32_t) * kFrontCap;
+        c.fS0 = (int32_t*)p; p += sizeof(int32_t) * c.FC;
+        c.fCs = (int32_t*)p; p += sizeof(int32_t) * c.FC;
+        c.fL0 = (int32_t*)p; p += sizeof(int32_t) * c.FC;
+        c.fCl = (int32_t*)p; p += sizeof(int32_t) * c.FC;
+        c.fNew = (int32_t*)p; p += sizeof(int32_t) * c.FC;
+        c.fSlot = (int32_t*)p; p += sizeof(int32_t) * c.FC;
     }
     const uint64_t t0 = wall_clock64();
     if (a.mode == MODE_SOLVE) {
@@ -2068,11 +2071,12 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 &
 
 // ------------------------------------------------------------ launchers
 size_t lds_bytes(int threads, int words, int awords) {
+    const size_t fc = threads > kFrontCap ? (size_t)threads : (size_t)kFrontCap;
     return sizeof(uint32_t) * ((size_t)words + (size_t)awords) + sizeof(unsigned long long) * kMaxW +
-           sizeof(int32_t) * (size_t)threads + sizeof(int32_t) * 6 * (size_t)kFrontCap +
+           sizeof(int32_t) * (size_t)threads + sizeof(int32_t) * 6 * fc +
            (sizeof(unsigned long long) + 2 * sizeof(int32_t)) * (size_t)kWinCap +
            (sizeof(unsigned long long) + 4 * sizeof(int32_t)) * (size_t)kImplCap +
-           sizeof(unsigned long long) * ((size_t)kFrontCap + (size_t)threads);
+           sizeof(unsigned long long) * (fc + (size_t)threads);
 }
 
 template <int LR, int EN>

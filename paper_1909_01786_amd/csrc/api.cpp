@@ -24,7 +24,7 @@
 #include "train.h"
 
 namespace asp {
-size_t lds_bytes(int threads, int words, int awords);
+size_t lds_bytes(int threads, int words, int awords, int learning);
 hipError_t launch_search(const KArgs& a, int threads, int grid, size_t lds, hipStream_t s);
 hipError_t set_max_lds(int threads, size_t lds);
 }  // namespace asp
@@ -276,7 +276,7 @@ int32_t make_plan(const std::vector<const HostProgram*>& progs, const asp_option
         lc.awords = (int32_t)((amax + 1 + 31) / 32);
         const int ci = (int)P.classes.size();
         lc.threads = (class_threads && ci < 4 && class_threads[ci] > 0) ? class_threads[ci] : threads;
-        lc.lds = lds_bytes(lc.threads, lc.words, lc.awords);
+        lc.lds = lds_bytes(lc.threads, lc.words, lc.awords, P.learning);
         P.classes.push_back(lc);
     }
     uint64_t o = 0;

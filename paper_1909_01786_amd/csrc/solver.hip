@@ -55,7 +55,8 @@ constexpr int kFrontCap = 128;   // frontier records kept in LDS (at least; one 
 constexpr int kWinBits = 8;
 constexpr int kWinCap = 1 << kWinBits;   // LDS winner table (variables implied in a round)
 constexpr int kWinProbe = 32;
-constexpr int kImplCap = 128;    // LDS implication slots (Deps candidate and record)
+constexpr int kImplCap = 128;    // LDS implication slots (Deps candidate and record; at
+                                 // least, one per thread for wider workgroups)
 constexpr uint32_t SLOT_TAG = 0x80000000u;
 constexpr int kLitBatch = 4;     // literals of a long nogood loaded together in a visit
 
@@ -123,6 +124,7 @@ struct Ctx {
     Scr* scr;
     int32_t W, T, tid, lane, wid, nw;
     int32_t FC;             // frontier records in LDS: max(T, kFrontCap)
+    int32_t IC;             // implication slots in LDS: max(T, kImplCap)
     int32_t decision, fallback_after, learning;
     int32_t ext;            // extended search: several answer sets, restarts, activity,
                             // several conflicts learned per step (compile-time in k_search)
@@ -754,8 +756,8 @@ DEV void visit_one(Ctx& c, const Ctl& k, int id, const MapEntry& e, uint32_t eid
         }
         int first = 0;
         const int t = tab_insert(c, x, first);
-        const int sl = c.W == 1 ? atomicAdd(&c.scr->nimpl, 1) : kImplCap;
-        if (sl < kImplCap) {
+        const int sl = c.W == 1 ? atomicAdd(&c.scr->nimpl, 1) : c.IC;
+        if (sl < c.IC) {
             if (inl) {
                 s0 = u == e.o1 ? e.a1 : e.a2;
                 s1 = s0 + (u == e.o1 ? e.n1 : e.n2);
@@ -2018,6 +2020,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 &
     c.wid = threadIdx.x >> 6;
     c.nw = MAXT / 64;
     c.FC = MAXT > kFrontCap ? MAXT : kFrontCap;
+    c.IC = MAXT > kImplCap ? MAXT : kImplCap;
     c.scr = &scr;
     c.my_visits = c.my_checks = 0ull;
     {
@@ -2025,17 +2028,21 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 &
         unsigned char* p = (unsigned char*)smem64;
         c.sB = (unsigned long long*)p; p += sizeof(unsigned long long) * kMaxW;
         c.tWin = (unsigned long long*)p; p += sizeof(unsigned long long) * kWinCap;
-        c.iDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * kImplCap;
+        c.iDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * c.IC;
         c.fDeps = (unsigned long long*)p; p += sizeof(unsigned long long) * c.FC;
-        c.sTile = (unsigned long long*)p; p += sizeof(unsigned long long) * MAXT;
+        c.sTile = nullptr;   // Res-learning only
+        if (LR == LEARN_RES) {
+            c.sTile = (unsigned long long*)p;
+            p += sizeof(unsigned long long) * MAXT;
+        }
         c.valb = (uint32_t*)p; p += sizeof(uint32_t) * a.words;
         c.lm = (uint32_t*)p; p += sizeof(uint32_t) * a.awords;
         c.tKey = (int32_t*)p; p += sizeof(int32_t) * kWinCap;
         c.tCode = (int32_t*)p; p += sizeof(int32_t) * kWinCap;
-        c.iS0 = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
-        c.iCs = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
-        c.iL0 = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
-        c.iCl = (int32_t*)p; p += sizeof(int32_t) * kImplCap;
+        c.iS0 = (int32_t*)p; p += sizeof(int32_t) * c.IC;
+        c.iCs = (int32_t*)p; p += sizeof(int32_t) * c.IC;
+        c.iL0 = (int32_t*)p; p += sizeof(int32_t) * c.IC;
+        c.iCl = (int32_t*)p; p += sizeof(int32_t) * c.IC;
         c.sOff = (int32_t*)p; p += sizeof(int32_t) * MAXT;
         c.fS0 = (int32_t*)p; p += sizeof(int32_t) * c.FC;
         c.fCs = (int32_t*)p; p += sizeof(int32_t) * c.FC;
@@ -2070,13 +2077,14 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu((EN == 0 &
 }
 
 // ------------------------------------------------------------ launchers
-size_t lds_bytes(int threads, int words, int awords) {
+size_t lds_bytes(int threads, int words, int awords, int learning) {
     const size_t fc = threads > kFrontCap ? (size_t)threads : (size_t)kFrontCap;
+    const size_t ic = threads > kImplCap ? (size_t)threads : (size_t)kImplCap;
     return sizeof(uint32_t) * ((size_t)words + (size_t)awords) + sizeof(unsigned long long) * kMaxW +
            sizeof(int32_t) * (size_t)threads + sizeof(int32_t) * 6 * fc +
            (sizeof(unsigned long long) + 2 * sizeof(int32_t)) * (size_t)kWinCap +
-           (sizeof(unsigned long long) + 4 * sizeof(int32_t)) * (size_t)kImplCap +
-           sizeof(unsigned long long) * (fc + (size_t)threads);
+           (sizeof(unsigned long long) + 4 * sizeof(int32_t)) * ic +
+           sizeof(unsigned long long) * (fc + (learning == LEARN_RES ? (size_t)threads : 0));
 }
 
 template <int LR, int EN>

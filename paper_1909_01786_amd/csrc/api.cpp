@@ -145,7 +145,7 @@ struct asp_batch {
     ScorerPlan scorer;
     uint8_t* arena = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_fork = nullptr;
-    std::vector<hipStream_t> streams;    // one per launch class (default priority)
+    std::vector<hipStream_t> streams;    // four, one per launch class (default priority)
     std::vector<hipEvent_t> ev_start, ev_join;  // per launch class (timed)
     bool timed = false;
     bool class_timed = false;                    // ev_start/ev_join hold the last launches
@@ -1393,6 +1393,24 @@ int32_t asp_batch_train_readout(asp_batch* b, const asp_scorer_weights* w, void*
     return ASP_OK;
 }
 
+// The launch classes of a batch run on streams of its own, all four of them
+// created together the first time: the runtime binds each new stream to the
+// least used of its hardware queues (four per process by default), so four
+// streams created back to back take four distinct queues, and destroying the
+// four together leaves the queues as evenly used as before.  Running a class
+// on the caller's stream instead, or creating only as many streams as there
+// are classes, lets the counts drift apart until two classes share a queue
+// and run one after the other.
+static hipError_t class_streams(asp_batch* b) {
+    while (b->streams.size() < 4) {
+        hipStream_t t;
+        hipError_t e = hipStreamCreateWithFlags(&t, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        b->streams.push_back(t);
+    }
+    return hipSuccess;
+}
+
 int32_t asp_solve_batch(asp_batch* b, void* stream, const asp_limits* lim) {
     if (!b || !b->bound) return fail(ASP_E_STATE, "batch not bound");
     if (b->opt.decision == ASP_DECISION_SCORE && b->n_ready < b->plan.n)
@@ -1414,14 +1432,7 @@ int32_t asp_solve_batch(asp_batch* b, void* stream, const asp_limits* lim) {
         b->ev_start.push_back(e0);
         b->ev_join.push_back(e1);
     }
-    // class 0 runs on the caller's stream, the others on internal streams:
-    // with the caller's stream that is at most four streams, one per
-    // hardware queue, so every class can run at once
-    while (nc > 1 && b->streams.size() < nc - 1) {
-        hipStream_t t;
-        HIPCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
-        b->streams.push_back(t);
-    }
+    if (nc > 1) HIPCHK(class_streams(b));
     HIPCHK(hipEventRecord(b->ev0, s));
     if (nc == 1) {
         const LaunchClass& lc = b->plan.classes[0];
@@ -1438,13 +1449,13 @@ int32_t asp_solve_batch(asp_batch* b, void* stream, const asp_limits* lim) {
             const LaunchClass& lc = b->plan.classes[c];
             KArgs a = make_args(b->plan, b->arena, MODE_SOLVE, lc);
             apply_limits(a, b->plan, lim, di);
-            hipStream_t cs = c == 0 ? s : b->streams[c - 1];
-            if (c > 0) HIPCHK(hipStreamWaitEvent(cs, b->ev_fork, 0));
+            hipStream_t cs = b->streams[c];
+            HIPCHK(hipStreamWaitEvent(cs, b->ev_fork, 0));
             HIPCHK(hipEventRecord(b->ev_start[c], cs));
             HIPCHK(launch_search(a, lc.threads, lc.count, lc.lds, cs));
             HIPCHK(hipEventRecord(b->ev_join[c], cs));
         }
-        for (size_t c = 1; c < nc; ++c) HIPCHK(hipStreamWaitEvent(s, b->ev_join[c], 0));
+        for (size_t c = 0; c < nc; ++c) HIPCHK(hipStreamWaitEvent(s, b->ev_join[c], 0));
     }
     HIPCHK(hipEventRecord(b->ev1, s));
     b->timed = true;
@@ -1473,11 +1484,7 @@ int32_t asp_solve_batch_graph(asp_batch* b, void* stream, const asp_limits* lim)
         HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         b->ev_cjoin.push_back(e);
     }
-    while (nc > 1 && b->streams.size() < nc - 1) {
-        hipStream_t t;
-        HIPCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
-        b->streams.push_back(t);
-    }
+    if (nc > 1) HIPCHK(class_streams(b));
     if (!b->gexec || b->gstream != s || b->glim.max_conflicts != L.max_conflicts ||
         b->glim.max_ms != L.max_ms) {
         if (b->gexec) {
@@ -1491,12 +1498,12 @@ int32_t asp_solve_batch_graph(asp_batch* b, void* stream, const asp_limits* lim)
             const LaunchClass& lc = b->plan.classes[c];
             KArgs a = make_args(b->plan, b->arena, MODE_SOLVE, lc);
             apply_limits(a, b->plan, &L, di);
-            hipStream_t cs = c == 0 ? s : b->streams[c - 1];
-            if (c > 0) e = hipStreamWaitEvent(cs, b->ev_fork, 0);
+            hipStream_t cs = nc > 1 ? b->streams[c] : s;
+            if (nc > 1) e = hipStreamWaitEvent(cs, b->ev_fork, 0);
             if (e == hipSuccess) e = launch_search(a, lc.threads, lc.count, lc.lds, cs);
-            if (e == hipSuccess && c > 0) e = hipEventRecord(b->ev_cjoin[c], cs);
+            if (e == hipSuccess && nc > 1) e = hipEventRecord(b->ev_cjoin[c], cs);
         }
-        for (size_t c = 1; c < nc && e == hipSuccess; ++c) e = hipStreamWaitEvent(s, b->ev_cjoin[c], 0);
+        for (size_t c = 0; c < nc && nc > 1 && e == hipSuccess; ++c) e = hipStreamWaitEvent(s, b->ev_cjoin[c], 0);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(s, &g);
         if (e != hipSuccess) return fail(ASP_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));

@@ -249,9 +249,25 @@ def write_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, config):
     }
     nc = len(config.get("class_threads", [])) or 4
     out["launch_bytes"] = out["launch_bytes"][-nc:]
+    # one file per kernel sources, one run per schedule measured with them
+    runs = []
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            t = json.load(fh)
+        if t.get("kernel_sha") == out["kernel_sha"]:
+            runs = [r for r in _traffic_runs(t) if r.get("config") != config]
+    except OSError:
+        pass
+    run = {k: v for k, v in out.items() if k != "kernel_sha"}
     with open(TRAFFIC_JSON, "w") as fh:
-        json.dump(out, fh, indent=1)
+        json.dump({"kernel_sha": out["kernel_sha"], "runs": runs + [run]}, fh, indent=1)
     print(json.dumps(out))
+
+
+def _traffic_runs(t):
+    """The measured runs of a traffic file (a single run at the top level
+    in files written before it held several schedules)."""
+    return t["runs"] if "runs" in t else [{k: v for k, v in t.items() if k != "kernel_sha"}]
 
 
 def traffic_for(config, launch_index):
@@ -263,16 +279,19 @@ def traffic_for(config, launch_index):
             t = json.load(fh)
     except OSError:
         return None
-    tc = t.get("config", {})
     if t.get("kernel_sha") != kernel_hash():
         return None
-    if any(tc.get(k) != config.get(k) for k in ("n", "seed", "budget", "W", "classes")):
-        return None
-    a, b = tc.get("class_threads", []), config.get("class_threads", [])
-    if launch_index >= len(a) or launch_index >= len(b) or a[launch_index] != b[launch_index]:
-        return None
-    lb = t.get("launch_bytes", [])
-    return lb[launch_index] if launch_index < len(lb) else None
+    for r in _traffic_runs(t):
+        tc = r.get("config", {})
+        if any(tc.get(k) != config.get(k) for k in ("n", "seed", "budget", "W", "classes")):
+            continue
+        a, b = tc.get("class_threads", []), config.get("class_threads", [])
+        if launch_index >= len(a) or launch_index >= len(b) or a[launch_index] != b[launch_index]:
+            continue
+        lb = r.get("launch_bytes", [])
+        if launch_index < len(lb):
+            return lb[launch_index]
+    return None
 
 
 # ------------------------------------------------------------ runs

@@ -382,10 +382,12 @@ int32_t asp_batch_bind(asp_batch *batch, void *dev_arena, uint64_t bytes,
                        void *stream);
 
 /* Enqueue the batched solve on stream (asynchronous): one launch per LDS
- * class -- the largest class on `stream` itself, the others forked onto
- * internal streams after the work already on `stream` and joined back into
- * it (at most four streams, so the classes run at once); each workgroup
- * solves one instance to a verdict.  Results stay in the arena. */
+ * class, each forked onto one of four streams the batch creates together
+ * at its first multi-class solve (so that each takes its own hardware
+ * queue and the classes run at once), after the work already on `stream`,
+ * and joined back into it; a single class launches on `stream` itself.
+ * Each workgroup solves one instance to a verdict.  Results stay in the
+ * arena. */
 int32_t asp_solve_batch(asp_batch *batch, void *stream, const asp_limits *lim);
 
 /* The same batched solve as one HIP graph launch: the first call (and any

@@ -4,7 +4,11 @@ A schedule (number of LDS size classes, threads per workgroup of each class)
 changes how the batch is laid onto the GPU, never its results: each candidate
 is timed on the batch itself (one untimed launch, then `reps` timed ones with
 HIP events), its verdicts and search counters are checked equal to the first
-candidate's, and the fastest schedule is returned.
+candidate's, and the fastest schedule is returned.  The timed launches are
+replays of the batch's HIP graph, as in the benchmark's timed steps: eager
+launches of the classes can land on one hardware queue and run one after
+the other, which would time the runtime's stream placement rather than the
+schedule.
 
     from paper_1909_01786_amd.autotune import autotune
     best, table = autotune(programs, P.limits(2000, 150000))
@@ -30,7 +34,8 @@ _COUNTERS = ("rounds", "visits", "literal_checks", "propagations", "decisions", 
              "learned", "learned_len", "trace_hash")
 
 
-def autotune(programs, lim, candidates=CANDIDATES, device="cuda", reps: int = 1, log=None):
+def autotune(programs, lim, candidates=CANDIDATES, device="cuda", reps: int = 1, log=None,
+             graph: bool = True):
     """programs: encoded Programs; returns ((classes, class_threads), table)
     where table lists (classes, class_threads, ms) per candidate.  The first
     candidate gets one untimed launch (the code object's first use); every
@@ -44,11 +49,11 @@ def autotune(programs, lim, candidates=CANDIDATES, device="cuda", reps: int = 1,
         with torch.cuda.stream(stream):
             b.bind(device, stream=stream)
         if ref is None:
-            b.solve(lim)
+            b.solve(lim, graph=graph)
             torch.cuda.synchronize()
         ms = []
         for _ in range(reps):
-            b.solve(lim)
+            b.solve(lim, graph=graph)
             torch.cuda.synchronize()
             ms.append(b.last_ms())
         verd, _, stats = b.results()

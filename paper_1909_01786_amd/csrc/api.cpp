@@ -1394,13 +1394,11 @@ int32_t asp_batch_train_readout(asp_batch* b, const asp_scorer_weights* w, void*
 }
 
 // The launch classes of a batch run on streams of its own, all four of them
-// created together the first time: the runtime binds each new stream to the
-// least used of its hardware queues (four per process by default), so four
-// streams created back to back take four distinct queues, and destroying the
-// four together leaves the queues as evenly used as before.  Running a class
-// on the caller's stream instead, or creating only as many streams as there
-// are classes, lets the counts drift apart until two classes share a queue
-// and run one after the other.
+// created together the first time, every class on one of them, so that the
+// classes can run at once.  Which hardware queue a stream takes is the
+// runtime's choice (four queues per process by default): two classes that
+// land on one queue run one after the other, with the same results.  The
+// graph replay (asp_solve_batch_graph) overlaps them.
 static hipError_t class_streams(asp_batch* b) {
     while (b->streams.size() < 4) {
         hipStream_t t;
